@@ -1,0 +1,272 @@
+/* CPU oracle for dynamic-graph random walks.  TEST INFRASTRUCTURE ONLY: see
+ * fw_oracle.h.  Plain C, single-threaded, written for checking by eye. */
+#include "fw_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x64-10 (Salmon et al., SC 2011, section 4): each round multiplies */
+/* words 0 and 2 by the two round constants, swaps and xors the high halves */
+/* with words 1, 3 and the round key; the key is bumped by the Weyl          */
+/* constants (golden ratio, sqrt(3) - 1) between rounds.                     */
+/* ---------------------------------------------------------------------- */
+static const uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ull;
+static const uint64_t PHILOX_M1 = 0xCA5A826395121157ull;
+static const uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ull;
+static const uint64_t PHILOX_W1 = 0xBB67AE8584CAA73Bull;
+
+static void mul128(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+  unsigned __int128 p = (unsigned __int128)a * b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void fwo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    uint64_t hi0, lo0, hi1, lo1;
+    mul128(PHILOX_M0, x0, &hi0, &lo0);
+    mul128(PHILOX_M1, x2, &hi1, &lo1);
+    uint64_t y0 = hi1 ^ x1 ^ k0;
+    uint64_t y1 = lo1;
+    uint64_t y2 = hi0 ^ x3 ^ k1;
+    uint64_t y3 = lo0;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+uint64_t fwo_draw(uint64_t seed, uint64_t qid, uint64_t t) {
+  uint64_t ctr[4] = {qid, t, 0, 0};
+  uint64_t key[2] = {seed, 0};
+  uint64_t out[4];
+  fwo_philox4x64_10(ctr, key, out);
+  return out[0];
+}
+
+uint64_t fwo_scale(uint64_t u, uint64_t total) {
+  unsigned __int128 p = (unsigned __int128)u * total;
+  return (uint64_t)(p >> 64);
+}
+
+/* Inverse transform sampling (section 2.2): the first index whose inclusive
+ * prefix sum exceeds r. */
+int64_t fwo_pick(const uint64_t* w, uint64_t d, uint64_t r) {
+  uint64_t prefix = 0;
+  for (uint64_t i = 0; i < d; ++i) {
+    prefix += w[i];
+    if (prefix > r) return (int64_t)i;
+  }
+  return -1;
+}
+
+static uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+/* Eq. 2 with a = p (return) and b = q (in-out): the relative chances are
+ * 1/p, 1, 1/q = p_den/p_num, 1, q_den/q_num.  Scale by p_num * q_num and
+ * divide out the common factor. */
+int fwo_node2vec_factors(uint32_t p_num, uint32_t p_den, uint32_t q_num, uint32_t q_den,
+                         fwo_params* out) {
+  if (!out || !p_num || !p_den || !q_num || !q_den) return FWO_EINVAL;
+  uint64_t ret = (uint64_t)p_den * q_num;
+  uint64_t in = (uint64_t)p_num * q_num;
+  uint64_t outf = (uint64_t)p_num * q_den;
+  uint64_t g = gcd64(gcd64(ret, in), outf);
+  ret /= g;
+  in /= g;
+  outf /= g;
+  if (ret > 0xFFFFFFFFull || in > 0xFFFFFFFFull || outf > 0xFFFFFFFFull) return FWO_EINVAL;
+  out->f_ret = (uint32_t)ret;
+  out->f_in = (uint32_t)in;
+  out->f_out = (uint32_t)outf;
+  return FWO_OK;
+}
+
+int fwo_validate(const fwo_graph* g) {
+  if (!g || !g->offsets || (g->n_edges && !g->adj)) return FWO_EINVAL;
+  if (g->n_vertices >= 0xFFFFFFFFull) return FWO_EINVAL;
+  if (g->offsets[0] != 0 || g->offsets[g->n_vertices] != g->n_edges) return FWO_EINVAL;
+  for (uint64_t v = 0; v < g->n_vertices; ++v) {
+    uint64_t b = g->offsets[v], e = g->offsets[v + 1];
+    if (e < b || e > g->n_edges) return FWO_EINVAL;
+    for (uint64_t i = b; i < e; ++i) {
+      if (g->adj[i] >= g->n_vertices) return FWO_EINVAL;
+      if (i > b && g->adj[i] <= g->adj[i - 1]) return FWO_EINVAL;
+    }
+  }
+  return FWO_OK;
+}
+
+static int cmp_u32(const void* a, const void* b) {
+  uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Is u a neighbour of v?  Rows are sorted, so libc bsearch answers it. */
+static int is_neighbour(const fwo_graph* g, uint32_t v, uint32_t u) {
+  uint64_t b = g->offsets[v], e = g->offsets[v + 1];
+  if (e == b) return 0;
+  return bsearch(&u, g->adj + b, (size_t)(e - b), sizeof(uint32_t), cmp_u32) != NULL;
+}
+
+static int check_params(const fwo_graph* g, int algo, const fwo_params* p) {
+  if (algo == FWO_DEEPWALK) return FWO_OK;
+  if (!p) return FWO_EINVAL;
+  if (algo == FWO_NODE2VEC) {
+    if (p->f_ret == 0 && p->f_in == 0 && p->f_out == 0) return FWO_EINVAL;
+    return FWO_OK;
+  }
+  if (algo == FWO_METAPATH) {
+    if (!g->labels || p->schema_len < 1 || p->schema_len > 16) return FWO_EINVAL;
+    return FWO_OK;
+  }
+  return FWO_EINVAL;
+}
+
+/* Section 2.1: weighted DeepWalk f(e(v,u)) = w(v,u); node2vec multiplies the
+ * weight by Eq. 2, where dist(v',u) = 0 means u is v', dist 1 means u is a
+ * neighbour of v', and every other neighbour of v is at distance 2; MetaPath
+ * multiplies the weight by Eq. 1, the indicator that the edge label equals
+ * the schema label of this hop.  At the first hop node2vec has no v' and uses
+ * the weight alone. */
+int fwo_transition_weights(const fwo_graph* g, int algo, const fwo_params* p, uint32_t prev,
+                           uint32_t cur, uint32_t t, uint64_t* w_out) {
+  if (!g || cur >= g->n_vertices) return FWO_EINVAL;
+  int rc = check_params(g, algo, p);
+  if (rc) return rc;
+  if (algo == FWO_NODE2VEC && t > 0 && prev >= g->n_vertices) return FWO_EINVAL;
+  uint64_t b = g->offsets[cur], d = g->offsets[cur + 1] - b;
+  for (uint64_t i = 0; i < d; ++i) {
+    uint64_t w = g->weights ? g->weights[b + i] : 1;
+    uint32_t u = g->adj[b + i];
+    uint64_t f = 1;
+    if (algo == FWO_NODE2VEC && t > 0) {
+      if (u == prev)
+        f = p->f_ret;
+      else if (is_neighbour(g, prev, u))
+        f = p->f_in;
+      else
+        f = p->f_out;
+    } else if (algo == FWO_METAPATH) {
+      f = (g->labels[b + i] == p->schema[t % p->schema_len]) ? 1 : 0;
+    }
+    w_out[i] = w * f;
+  }
+  return FWO_OK;
+}
+
+/* The total of one step must fit in 64 bits: max_w * max_f * max_deg < 2^64. */
+static int check_overflow(const fwo_graph* g, int algo, const fwo_params* p) {
+  uint64_t max_w = 1, max_deg = 0, max_f = 1;
+  if (g->weights) {
+    max_w = 0;
+    for (uint64_t e = 0; e < g->n_edges; ++e)
+      if (g->weights[e] > max_w) max_w = g->weights[e];
+  }
+  for (uint64_t v = 0; v < g->n_vertices; ++v) {
+    uint64_t d = g->offsets[v + 1] - g->offsets[v];
+    if (d > max_deg) max_deg = d;
+  }
+  if (algo == FWO_NODE2VEC) {
+    max_f = p->f_ret;
+    if (p->f_in > max_f) max_f = p->f_in;
+    if (p->f_out > max_f) max_f = p->f_out;
+    if (max_f == 0) max_f = 1;
+  }
+  unsigned __int128 bound = (unsigned __int128)max_w * max_f * max_deg;
+  return (bound >> 64) ? FWO_EOVERFLOW : FWO_OK;
+}
+
+static uint64_t max_degree(const fwo_graph* g) {
+  uint64_t m = 0;
+  for (uint64_t v = 0; v < g->n_vertices; ++v) {
+    uint64_t d = g->offsets[v + 1] - g->offsets[v];
+    if (d > m) m = d;
+  }
+  return m;
+}
+
+/* One query: Algorithm 1's loop with inverse transform sampling. */
+static int walk_one(const fwo_graph* g, int algo, const fwo_params* p, uint32_t start,
+                    uint64_t qid, uint32_t length, uint64_t seed, uint64_t* wbuf,
+                    uint32_t* row) {
+  if (start >= g->n_vertices) return FWO_EINVAL;
+  row[0] = start;
+  for (uint32_t t = 0; t < length; ++t) {
+    uint32_t cur = row[t];
+    uint32_t prev = t > 0 ? row[t - 1] : FWO_END;
+    uint64_t b = g->offsets[cur], d = g->offsets[cur + 1] - b;
+    int rc = fwo_transition_weights(g, algo, p, prev, cur, t, wbuf);
+    if (rc) return rc;
+    uint64_t total = 0;
+    for (uint64_t i = 0; i < d; ++i) total += wbuf[i];
+    if (total == 0) {
+      for (uint32_t s = t + 1; s <= length; ++s) row[s] = FWO_END;
+      return FWO_OK;
+    }
+    uint64_t r = fwo_scale(fwo_draw(seed, qid, t), total);
+    int64_t i = fwo_pick(wbuf, d, r);
+    row[t + 1] = g->adj[b + (uint64_t)i];
+  }
+  return FWO_OK;
+}
+
+static int walk_setup(const fwo_graph* g, int algo, const fwo_params* p, uint64_t** wbuf) {
+  if (!g || !g->offsets) return FWO_EINVAL;
+  int rc = check_params(g, algo, p);
+  if (rc) return rc;
+  rc = check_overflow(g, algo, p);
+  if (rc) return rc;
+  uint64_t md = max_degree(g);
+  *wbuf = (uint64_t*)malloc((md ? md : 1) * sizeof(uint64_t));
+  return *wbuf ? FWO_OK : FWO_ENOMEM;
+}
+
+int fwo_walk(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
+             uint64_t n, uint32_t length, uint64_t seed, uint64_t qid_base,
+             uint32_t* out_paths) {
+  if (n == 0) return FWO_OK;
+  if (!starts || !out_paths) return FWO_EINVAL;
+  uint64_t* wbuf = NULL;
+  int rc = walk_setup(g, algo, p, &wbuf);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < n && rc == FWO_OK; ++i)
+    rc = walk_one(g, algo, p, starts[i], qid_base + i, length, seed, wbuf,
+                  out_paths + i * ((uint64_t)length + 1));
+  free(wbuf);
+  return rc;
+}
+
+int fwo_walk_ids(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
+                 const uint64_t* qids, uint64_t m, uint32_t length, uint64_t seed,
+                 uint32_t* out_paths) {
+  if (m == 0) return FWO_OK;
+  if (!starts || !qids || !out_paths) return FWO_EINVAL;
+  uint64_t* wbuf = NULL;
+  int rc = walk_setup(g, algo, p, &wbuf);
+  if (rc) return rc;
+  for (uint64_t j = 0; j < m && rc == FWO_OK; ++j)
+    rc = walk_one(g, algo, p, starts[qids[j]], qids[j], length, seed, wbuf,
+                  out_paths + j * ((uint64_t)length + 1));
+  free(wbuf);
+  return rc;
+}

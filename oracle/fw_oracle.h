@@ -1,0 +1,101 @@
+/* CPU oracle for dynamic-graph random walks (DeepWalk, node2vec, MetaPath).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, single-threaded
+ * definition that the HIP library is checked against, bit for bit.  Only the
+ * test suite, the smoke check and the bench's CPU-baseline leg may load it;
+ * the product library never does, and the two share no code.
+ *
+ * What one walk computes (Algorithm 1, "Random Walk Computation Paradigm",
+ * section 2.1): from the start vertex, each step computes the transition
+ * weight of every neighbour of the current vertex (initialisation phase) and
+ * then picks one neighbour with probability proportional to it (selection
+ * phase).  The weights are those of section 2.1: the edge weight (weighted
+ * DeepWalk), Eq. 2 times the edge weight (node2vec), Eq. 1 times the edge
+ * weight (MetaPath).  The pick is inverse transform sampling (section 2.2)
+ * over exact integer prefix sums, driven by one Philox4x64-10 draw per step
+ * (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC 2011).  Both the reservoir samplers of section 4 (Propositions 1 and 2)
+ * and this pick select neighbour i with probability w'_i / sum(w').
+ */
+#ifndef FW_ORACLE_H
+#define FW_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (same numeric values as the library's, defined separately). */
+#define FWO_OK 0
+#define FWO_EINVAL (-1)
+#define FWO_ENOMEM (-2)
+#define FWO_EOVERFLOW (-3)
+
+#define FWO_DEEPWALK 0
+#define FWO_NODE2VEC 1
+#define FWO_METAPATH 2
+
+#define FWO_END 0xFFFFFFFFu /* path padding after an early end */
+
+/* Host CSR view.  offsets[V+1], adj[E] with each row sorted ascending;
+ * weights[E] (NULL = every weight 1); labels[E] (NULL = no labels). */
+typedef struct {
+  uint64_t n_vertices, n_edges;
+  const uint64_t* offsets;
+  const uint32_t* adj;
+  const uint32_t* weights;
+  const uint8_t* labels;
+} fwo_graph;
+
+/* Integer node2vec factors (return, in-out: stay near prev, move away) and
+ * the MetaPath label schema, cycled: hop t uses schema[t mod schema_len]. */
+typedef struct {
+  uint32_t f_ret, f_in, f_out;
+  uint32_t schema_len;
+  uint8_t schema[16];
+} fwo_params;
+
+/* Philox4x64 with 10 rounds; out[0..3] for counter ctr[0..3], key key[0..1]. */
+void fwo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* The step draw: word 0 of Philox4x64-10(counter = (qid, t, 0, 0),
+ * key = (seed, 0)). */
+uint64_t fwo_draw(uint64_t seed, uint64_t qid, uint64_t t);
+
+/* floor(u * total / 2^64): maps a uniform 64-bit word to [0, total). */
+uint64_t fwo_scale(uint64_t u, uint64_t total);
+
+/* Inverse CDF: smallest i with w[0] + ... + w[i] > r, or -1 when r is not
+ * below the total. */
+int64_t fwo_pick(const uint64_t* w, uint64_t d, uint64_t r);
+
+/* p, q as rationals -> reduced integer factors proportional to (1/p, 1, 1/q).
+ * Returns FWO_EINVAL for a zero numerator/denominator or factors >= 2^32. */
+int fwo_node2vec_factors(uint32_t p_num, uint32_t p_den, uint32_t q_num, uint32_t q_den,
+                         fwo_params* out);
+
+/* Checks the CSR: offsets[0] = 0, monotone, offsets[V] = E, every id < V,
+ * rows strictly ascending, V < 2^32 - 1. */
+int fwo_validate(const fwo_graph* g);
+
+/* Transition weights of every neighbour of `cur` at hop t (prev is ignored at
+ * t = 0).  w_out receives d(cur) values.  Returns FWO_OK or FWO_EINVAL. */
+int fwo_transition_weights(const fwo_graph* g, int algo, const fwo_params* p, uint32_t prev,
+                           uint32_t cur, uint32_t t, uint64_t* w_out);
+
+/* Walks n queries.  Query i has id qid_base + i and starts at starts[i];
+ * row i of out_paths (length + 1 entries) receives its path. */
+int fwo_walk(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
+             uint64_t n, uint32_t length, uint64_t seed, uint64_t qid_base,
+             uint32_t* out_paths);
+
+/* Walks the m queries qids[j] (start starts[qids[j]]), row j of out_paths. */
+int fwo_walk_ids(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
+                 const uint64_t* qids, uint64_t m, uint32_t length, uint64_t seed,
+                 uint32_t* out_paths);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,308 @@
+"""Pins of the CPU oracle to things other than itself.
+
+Each pin checks the oracle against a fact fixed outside its code: a published
+Philox known answer and numpy's independent Philox implementation; closed
+forms for the 64-bit scaling computed with Python integers; brute-force
+enumeration for the inverse-CDF pick; hand-worked transition weights; exact
+path distributions computed from graph distances (scipy's BFS) for Eq. 2 and
+from labels for Eq. 1, against which 10^6 oracle draws are chi-square tested;
+algorithm identities; and walk invariants.  The same pins run against planted
+mistakes in the oracle (test_oracle_mutants) to show that they catch them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from helpers import END, chi2_pvalue, csr_from_edges, path_distribution, tiny6
+
+M64 = (1 << 64) - 1
+
+
+def _numpy_philox_block(ctr, key):
+    """numpy's Philox increments its 256-bit counter before each block, so
+    start it one below."""
+    c = sum(int(x) << (64 * i) for i, x in enumerate(ctr))
+    c = (c - 1) % (1 << 256)
+    words = [(c >> (64 * i)) & M64 for i in range(4)]
+    bg = np.random.Philox(key=np.array([int(key[0]), int(key[1])], dtype=np.uint64),
+                         counter=np.array(words, dtype=np.uint64))
+    return [int(x) for x in bg.random_raw(4)]
+
+
+def pin_philox_kat():
+    # Published known answer for Philox4x64-10 at counter 0, key 0 (Random123
+    # distribution of Salmon et al., SC 2011).
+    got = [int(x) for x in oracle.philox4x64_10([0, 0, 0, 0], [0, 0])]
+    assert got == [0x16554D9ECA36314C, 0xDB20FE9D672D0FDC, 0xD7E772CEE186176B,
+                   0x7E68B68AEC7BA23B], [hex(x) for x in got]
+
+
+def pin_philox_numpy(cases=200):
+    rng = np.random.default_rng(7)
+    for i in range(cases):
+        ctr = [int(x) for x in rng.integers(0, 1 << 63, 4, dtype=np.uint64)]
+        if i % 4 == 0:
+            ctr[2] = ctr[3] = 0
+        if i % 5 == 0:
+            ctr[0] = M64
+        key = [int(x) for x in rng.integers(0, 1 << 63, 2, dtype=np.uint64)]
+        got = [int(x) for x in oracle.philox4x64_10(ctr, key)]
+        assert got == _numpy_philox_block(ctr, key), (ctr, key)
+
+
+def pin_draw_keying(cases=100):
+    """The step draw is word 0 of the block at counter (qid, t, 0, 0) and key
+    (seed, 0)."""
+    rng = np.random.default_rng(11)
+    for _ in range(cases):
+        seed, qid, t = (int(x) for x in rng.integers(0, 1 << 40, 3))
+        t %= 1000
+        assert oracle.draw(seed, qid, t) == _numpy_philox_block([qid, t, 0, 0], [seed, 0])[0]
+
+
+def pin_scale_closed_form():
+    """floor(u*T/2^64) == r exactly on the interval [ceil(r 2^64 / T),
+    ceil((r+1) 2^64 / T)), whose length is floor or ceil of 2^64/T."""
+    rng = np.random.default_rng(3)
+    totals = [1, 2, 3, 5, 7, 255, 1 << 20, (1 << 38) + 12345, (1 << 63) + 1, M64]
+    totals += [int(x) for x in rng.integers(1, 1 << 62, 20, dtype=np.uint64)]
+    two64 = 1 << 64
+    for T in totals:
+        for r in {0, 1, T // 2, T - 1, int(rng.integers(0, 1 << 62)) % T}:
+            if r >= T:
+                continue
+            lo = -(-r * two64 // T)
+            hi = -(-(r + 1) * two64 // T)
+            assert hi - lo in (two64 // T, -(-two64 // T))
+            assert oracle.scale(lo, T) == r, (T, r)
+            assert oracle.scale(hi - 1, T) == r, (T, r)
+            if lo > 0:
+                assert oracle.scale(lo - 1, T) == r - 1, (T, r)
+        assert oracle.scale(M64, T) == T - 1
+        assert oracle.scale(0, T) == 0
+
+
+def pin_pick_bruteforce():
+    """Enumerating every r in [0, T) hits index i exactly w_i times, and
+    index order follows r (inverse CDF in list order)."""
+    rng = np.random.default_rng(5)
+    vectors = [[1], [3], [0, 2], [2, 0], [1, 1, 1], [0, 0, 5, 0], [4, 0, 0, 1, 3]]
+    vectors += [list(rng.integers(0, 20, int(rng.integers(1, 40)))) for _ in range(30)]
+    for w in vectors:
+        T = int(sum(w))
+        if T == 0:
+            assert oracle.pick(w, 0) == -1
+            continue
+        picks = [oracle.pick(w, r) for r in range(T)]
+        assert picks == sorted(picks)
+        counts = np.bincount(picks, minlength=len(w))
+        assert counts.tolist() == [int(x) for x in w], (w, counts)
+        assert oracle.pick(w, T) == -1
+
+
+def _prm(case):
+    if case["algo"] == "node2vec":
+        return oracle.params(*case["factors"])
+    if case["algo"] == "metapath":
+        return oracle.params(schema=case["schema"])
+    return oracle.params()
+
+
+def pin_hand_weights():
+    for case in tiny6()[1]["cases"]:
+        g, _ = tiny6(weighted=case["weighted"])
+        prev = case["prev"] if case["prev"] is not None else 0xFFFFFFFF
+        got = oracle.transition_weights(g, case["algo"], _prm(case), prev, case["cur"], case["t"])
+        assert got.tolist() == case["expect"], (case, got)
+
+
+def _chi2_case(g, algo, start, length, factors=(1, 1, 1), schema=(), n=1_000_000, seed=2024):
+    dist = path_distribution(g, algo, start, length, factors, schema)
+    prm = oracle.params(*factors, schema=schema)
+    rows = oracle.walk(g, algo, prm, np.full(n, start, dtype=np.uint32), length, seed)
+    p = chi2_pvalue(rows, dist)
+    assert p > 1e-4, (algo, start, length, factors, schema, p)
+    return p
+
+
+def pin_chi2_paths(n=1_000_000):
+    """10^6 oracle walks of length 3 from one start (query ids 0..n-1 give
+    independent draws) against the exact path distribution."""
+    g, _ = tiny6()
+    _chi2_case(g, "deepwalk", 0, 3, n=n)
+    _chi2_case(g, "node2vec", 2, 3, factors=(1, 2, 4), n=n)
+    _chi2_case(g, "node2vec", 3, 3, factors=(4, 2, 1), n=n)
+    _chi2_case(g, "metapath", 1, 3, schema=(0, 1), n=n)
+    gu, _ = tiny6(weighted=False)
+    _chi2_case(gu, "metapath", 3, 3, schema=(1, 0, 2), n=n)
+
+
+def _python_walk(g, dist, algo, start, qid, length, seed, factors, schema):
+    """A walk rebuilt from independent parts: numpy's Philox for the draw,
+    Python integers for the scaling, chances from graph distances/labels."""
+    from helpers import chances
+    row = [start]
+    for t in range(length):
+        cur = row[-1]
+        prev = row[-2] if t > 0 else None
+        c = chances(g, dist, algo, cur, prev, t, factors, schema)
+        tot = sum(c)
+        if tot == 0:
+            return row + [END] * (length - t)
+        u = _numpy_philox_block([qid, t, 0, 0], [seed, 0])[0]
+        r = (u * tot) >> 64
+        acc = 0
+        for i, ci in enumerate(c):
+            acc += ci
+            if acc > r:
+                break
+        row.append(int(g.adj[int(g.offsets[cur]) + i]))
+    return row
+
+
+def pin_walk_rebuilt():
+    """Whole walks equal the rebuilt ones, for query ids with an offset."""
+    from helpers import hop_distances
+    g, _ = tiny6()
+    dist = hop_distances(g)
+    seed, L, base = 123456789, 6, 1000
+    starts = np.arange(40, dtype=np.uint32) % 6
+    for algo, f, sch in [("deepwalk", (1, 1, 1), ()), ("node2vec", (1, 2, 4), ()),
+                         ("metapath", (1, 1, 1), (0, 1))]:
+        rows = oracle.walk(g, algo, oracle.params(*f, schema=sch), starts, L, seed,
+                           qid_base=base)
+        for i, s in enumerate(starts):
+            exp = _python_walk(g, dist, algo, int(s), base + i, L, seed, f, sch)
+            assert rows[i].tolist() == exp, (algo, i, rows[i], exp)
+
+
+def pin_identities():
+    """node2vec with equal factors is DeepWalk; MetaPath whose schema matches
+    every label is unit-weight DeepWalk; both bit-exact."""
+    g, _ = tiny6()
+    starts = np.arange(6, dtype=np.uint32).repeat(50)
+    a = oracle.walk(g, "deepwalk", oracle.params(), starts, 12, 9)
+    for f in [(1, 1, 1), (3, 3, 3)]:
+        b = oracle.walk(g, "node2vec", oracle.params(*f), starts, 12, 9)
+        assert np.array_equal(a, b), f
+    gl = csr_from_edges(6, [(u, v, w, 3) for (u, v, w, _) in tiny6()[1]["edges"]],
+                        weights=False)
+    gu = csr_from_edges(6, tiny6()[1]["edges"], weights=False, labels=False)
+    a = oracle.walk(gu, "deepwalk", oracle.params(), starts, 12, 9)
+    b = oracle.walk(gl, "metapath", oracle.params(schema=[3]), starts, 12, 9)
+    assert np.array_equal(a, b)
+
+
+def pin_regular_uniform(n=200_000):
+    """Unweighted DeepWalk on a k-regular graph picks each neighbour with
+    probability 1/k (circulant graph C_12(1, 2, 5): 6-regular)."""
+    nv, k = 12, 6
+    edges = {tuple(sorted((i, (i + s) % nv))) for i in range(nv) for s in (1, 2, 5)}
+    g = csr_from_edges(nv, [(u, v, 1, 0) for (u, v) in sorted(edges)], weights=False)
+    rows = oracle.walk(g, "deepwalk", oracle.params(), np.zeros(n, np.uint32), 1, 77)
+    counts = np.bincount(rows[:, 1], minlength=nv)
+    nb = g.adj[int(g.offsets[0]):int(g.offsets[1])]
+    assert set(np.nonzero(counts)[0].tolist()) == set(nb.tolist())
+    from scipy.stats import chisquare
+    assert chisquare(counts[nb]).pvalue > 1e-4
+    assert len(nb) == k
+
+
+def pin_path_graph_edges():
+    """On a weighted path graph an interior vertex moves left with
+    probability w_left / (w_left + w_right)."""
+    edges = [(0, 1, 1, 0), (1, 2, 3, 0), (2, 3, 5, 0), (3, 4, 7, 0)]
+    g = csr_from_edges(5, edges)
+    n = 400_000
+    rows = oracle.walk(g, "deepwalk", oracle.params(), np.full(n, 2, np.uint32), 1, 5)
+    left = float((rows[:, 1] == 1).mean())
+    assert abs(left - 3 / 8) < 5 * np.sqrt(3 / 8 * 5 / 8 / n)
+
+
+def walk_invariants(g, algo, prm_tuple, starts, paths, schema=()):
+    """path[0] = start; each hop is an edge; MetaPath hops carry the schema
+    label; an early end happens exactly where no neighbour has positive
+    chance (degree 0 for DeepWalk/node2vec with positive factors; no label
+    match for MetaPath), and is padded to the end."""
+    off, adj = g.offsets, g.adj
+    L = paths.shape[1] - 1
+    assert np.array_equal(paths[:, 0], np.asarray(starts, dtype=np.uint32))
+    for row in paths:
+        for t in range(L):
+            cur, nxt = int(row[t]), int(row[t + 1])
+            if cur == END:
+                assert nxt == END
+                continue
+            b, e = int(off[cur]), int(off[cur + 1])
+            nb = adj[b:e]
+            if algo == "metapath":
+                ok = g.labels[b:e] == schema[t % len(schema)]
+                if g.weights is not None:
+                    ok &= g.weights[b:e] > 0
+            else:
+                ok = np.ones(e - b, bool) if g.weights is None else g.weights[b:e] > 0
+            if nxt == END:
+                assert not ok.any(), (row, t)
+            else:
+                j = np.searchsorted(nb, nxt)
+                assert j < e - b and nb[j] == nxt and ok[j], (row, t)
+
+
+def pin_invariants_rmat12():
+    import synth
+    g = synth.load_recipe_graph("rmat12_n2v", use_cache=False)
+    starts = np.arange(g.n_vertices, dtype=np.uint32)
+    paths = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts, 20, 42)
+    walk_invariants(g, "node2vec", (1, 2, 4), starts, paths)
+    labels = synth.labels_uniform(g, 5, 99)
+    g.labels = labels
+    sch = (0, 1, 2, 3, 4)
+    paths = oracle.walk(g, "metapath", oracle.params(schema=sch), starts, 20, 42)
+    walk_invariants(g, "metapath", None, starts, paths, schema=sch)
+
+
+def pin_errors():
+    g, _ = tiny6()
+    ok = oracle.params(1, 2, 4)
+    rc, _ = oracle.walk_status(g, "node2vec", ok, [6], 3, 1)
+    assert rc == oracle.EINVAL
+    rc, _ = oracle.walk_status(g, "node2vec", oracle.params(0, 0, 0), [0], 3, 1)
+    assert rc == oracle.EINVAL
+    gnl, _ = tiny6(labelled=False)
+    rc, _ = oracle.walk_status(gnl, "metapath", oracle.params(schema=[0]), [0], 3, 1)
+    assert rc == oracle.EINVAL
+    rc, _ = oracle.walk_status(g, "metapath", oracle.params(), [0], 3, 1)
+    assert rc == oracle.EINVAL
+    big = csr_from_edges(3, [(0, 1, 0xFFFFFFFF, 0), (0, 2, 1, 0)])
+    rc, _ = oracle.walk_status(big, "node2vec", oracle.params(0xFFFFFFFF, 1, 1), [0], 2, 1)
+    assert rc == oracle.EOVERFLOW
+    rc, _ = oracle.walk_status(big, "deepwalk", oracle.params(), [0], 2, 1)
+    assert rc == oracle.OK
+    bad = csr_from_edges(3, [(0, 1, 1, 0), (0, 2, 1, 0)])
+    bad.adj = bad.adj[[1, 0, 2, 3]].copy()
+    assert oracle.validate(bad) == oracle.EINVAL
+    assert oracle.validate(g) == oracle.OK
+
+
+def pin_zero_length_and_dead_ends():
+    g, _ = tiny6()
+    rows = oracle.walk(g, "deepwalk", oracle.params(), np.arange(6), 0, 1)
+    assert rows.shape == (6, 1) and rows[:, 0].tolist() == list(range(6))
+    # Schema (0, 1, 2) from vertex 1: hop 0 takes a label-0 edge to 0 or 2,
+    # hop 1 a label-1 edge; from 0 that edge leads to 2, and no edge at 2
+    # carries label 2, so those walks end at hop 2 and are padded.
+    rows = oracle.walk(g, "metapath", oracle.params(schema=[0, 1, 2]),
+                       np.full(2000, 1), 4, 3)
+    assert set(rows[:, 1].tolist()) <= {0, 2}
+    dead = (rows[:, 1] == 0) & (rows[:, 2] == 2)
+    assert dead.any()
+    assert (rows[dead, 3] == END).all() and (rows[dead, 4] == END).all()
+    live = rows[:, 3] != END
+    assert (rows[:, 3] != END).any()
+
+
+ALL_PINS = [pin_philox_kat, pin_philox_numpy, pin_draw_keying, pin_scale_closed_form,
+            pin_pick_bruteforce, pin_hand_weights, pin_walk_rebuilt, pin_chi2_paths, pin_identities,
+            pin_regular_uniform, pin_path_graph_edges, pin_errors,
+            pin_zero_length_and_dead_ends]

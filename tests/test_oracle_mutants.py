@@ -1,0 +1,54 @@
+"""Planted mistakes in the oracle (CPU only): each mutant copy of the oracle
+source, compiled on its own, must fail at least one pin.  This shows the pins
+would catch a dropped term, a wrong index or a transposed operand."""
+import ctypes
+import subprocess
+from pathlib import Path
+
+import pytest
+
+import oracle
+import oracle_pins as P
+
+SRC = Path(oracle.__file__).resolve().parent / "fw_oracle.c"
+
+MUTANTS = {
+    "pick_ge": ("if (prefix > r) return", "if (prefix >= r) return"),
+    "swap_return_out": ("f = p->f_ret;", "f = p->f_out;"),
+    "drop_in_factor": ("f = p->f_in;", "f = 1;"),
+    "schema_index": ("p->schema[t % p->schema_len]", "p->schema[(t + 1) % p->schema_len]"),
+    "first_hop_rule": ("if (algo == FWO_NODE2VEC && t > 0) {", "if (algo == FWO_NODE2VEC && t > 1) {"),
+    "draw_operands": ("fwo_draw(seed, qid, t)", "fwo_draw(seed, t, qid)"),
+    "philox_key_bump": ("k1 += PHILOX_W1;", "k1 += 0;"),
+    "philox_rounds": ("round < 10", "round < 9"),
+    "scale_bias": ("(unsigned __int128)u * total", "(unsigned __int128)(u >> 1) * total"),
+    "drop_weight": ("w_out[i] = w * f;", "w_out[i] = f;"),
+    "padding": ("for (uint32_t s = t + 1; s <= length; ++s)", "for (uint32_t s = t + 1; s < length; ++s)"),
+}
+
+
+@pytest.fixture(scope="module")
+def mutant_dir(tmp_path_factory):
+    return tmp_path_factory.mktemp("mutants")
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, mutant_dir, monkeypatch):
+    old, new = MUTANTS[name]
+    text = SRC.read_text()
+    assert text.count(old) >= 1, name
+    src = mutant_dir / f"{name}.c"
+    src.write_text(text.replace(old, new))
+    (mutant_dir / "fw_oracle.h").write_text((SRC.parent / "fw_oracle.h").read_text())
+    so = mutant_dir / f"lib{name}.so"
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", str(src), "-o", str(so)],
+                   check=True)
+    monkeypatch.setattr(oracle, "_lib", oracle.bind(ctypes.CDLL(str(so))))
+    failed = []
+    for pin in P.ALL_PINS + [P.pin_invariants_rmat12]:
+        try:
+            pin()
+        except AssertionError:
+            failed.append(pin.__name__)
+            break
+    assert failed, f"mutant {name} passed every pin"
