@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark: walk steps/s and HBM GB/s of the DGRW hot path on one MI355X.
+
+One step = one full pass of the hot path over the workload's query set: every
+hop of every query (degree lookup, on-the-fly transition weights, total,
+draw, inverse-CDF locate, emit), in one launch of the walker.  Inputs (graph,
+starts, output buffer) are resident in HBM before the timed region.
+
+Prints one JSON line (see the keys below).  The CPU baseline is the oracle
+(plain single-threaded C walker) run over a bounded sample of the same
+queries on the host's cores, sharded by query.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "walk steps/sec + HBM GB/s (node2vec, power-law graph); p50/p99 query latency"
+PEAK_HBM_GBPS = 8000.0
+
+WORKLOADS = {
+    "rmat22_n2v": "R-MAT scale 22 (a=.57 b=.19 c=.19), edge factor 16, symmetrised, self-loops "
+                  "and duplicates removed, sorted rows, ids relabelled; uint32 weights Zipf(1.2) "
+                  "clipped to [1,65535]; node2vec p=1 q=2 (integer factors 2,2,1); one query per "
+                  "vertex (4,194,304), 80 hops, Philox seed 42, uint64 offsets",
+    "rmat22_deepwalk": "same graph as rmat22_n2v; weighted DeepWalk; one query per vertex, 80 hops",
+    "rmat12_n2v": "R-MAT scale 12, edge factor 8; uint32 weights U[1,255]; node2vec p=2 q=1/2 "
+                  "(factors 1,2,4); one query per vertex (4096), 20 hops, seed 42",
+    "chunglu24_metapath": "Chung-Lu 2^24 vertices, gamma 2.1, ~253M stored edges, d_max ~0.94M; "
+                          "labels U{0..4}, no weights; MetaPath schema [0,1,2,3,4] cycled; one "
+                          "query per vertex (16,777,216), 20 hops",
+    "chunglu227m_n2v": "Chung-Lu 227M vertices, gamma 2.0, ~2.7B stored edges; weights U[1,1000]; "
+                       "node2vec p=1/2 q=2 (factors 4,2,1); 10M uniform starts, 80 hops",
+}
+
+# Bytes a hop must read/write (excluding N(prev), re-read from cache): per
+# attempted hop from v of degree d, offsets (16 B) plus `scan` bytes per
+# neighbour; per realised hop, `emit` more bytes.
+def byte_model(algo: str, weighted: bool, labelled: bool):
+    if algo == "deepwalk":
+        return dict(scan=4 if weighted else 0, emit=8)
+    if algo == "node2vec":
+        return dict(scan=8 if weighted else 4, emit=4)
+    return dict(scan=(1 + (4 if weighted else 0)), emit=8)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    for p in sorted((ROOT / "paper_2404_08364_amd" / "csrc").glob("*")):
+        h.update(p.read_bytes())
+    return h.hexdigest()[:12]
+
+
+def recipe_params(fw, recipe):
+    walk = recipe["walk"]
+    algo = walk["algo"]
+    if algo == "node2vec":
+        (pn, pd), (qn, qd) = walk["p"], walk["q"]
+        return algo, fw.make_params(fw.node2vec_factors(pn, pd, qn, qd)), walk
+    if algo == "metapath":
+        return algo, fw.make_params(schema=walk["schema"]), walk
+    return algo, None, walk
+
+
+def oracle_params(prm, algo):
+    import oracle
+    if prm is None:
+        return oracle.params()
+    return oracle.params(prm.f_ret, prm.f_in, prm.f_out,
+                         schema=list(prm.schema)[:prm.schema_len])
+
+
+def account(torch, paths, deg, model):
+    """Realised hops, attempted hops and algorithmic bytes of one pass."""
+    L = paths.shape[1] - 1
+    hops = 0
+    attempts = 0
+    scanned = 0
+    for t in range(L):
+        cur = paths[:, t]
+        live = cur != -1
+        n_live = int(live.sum())
+        if n_live == 0:
+            break
+        attempts += n_live
+        scanned += int(deg[cur[live].long()].sum())
+        hops += int((paths[:, t + 1] != -1).sum())
+    total = attempts * 16 + scanned * model["scan"] + hops * model["emit"]
+    return hops, attempts, scanned, total
+
+
+def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    # Calibrate on a small single-threaded sample, then size the real sample.
+    stride_q = np.arange(0, n, max(1, n // 4096), dtype=np.uint64)[:64]
+    t0 = time.perf_counter()
+    rows = oracle.walk_ids(g, algo, oprm, starts, stride_q, L, seed)
+    dt = max(time.perf_counter() - t0, 1e-4)
+    per_query = dt / len(stride_q)
+    m = int(min(n, max(64, target_s * threads / per_query)))
+    step = max(1, n // m)
+    qids = np.arange(0, n, step, dtype=np.uint64)[:m]
+    t0 = time.perf_counter()
+    rows = oracle.walk_ids_threaded(g, algo, oprm, starts, qids, L, seed, threads)
+    wall = time.perf_counter() - t0
+    hops = int((rows[:, 1:] != oracle.END).sum())
+    ok = bool(np.array_equal(gpu_rows_fn(qids), rows))
+    return dict(value=hops / wall, unit="walk steps/s", cores=threads, kind="oracle",
+                sample=f"{len(qids)} queries (every {step}-th query id), {hops} hops, "
+                       f"{wall:.1f} s wall on {threads} host threads",
+                parity_on_sample=ok)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat22_n2v", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="persistent", choices=["plain", "persistent", "auto"])
+    ap.add_argument("--compare-plain", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--use-graph", type=int, default=1)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(queries shard trivially across GPUs, see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2404_08364_amd import flowwalk as fw
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+
+    t0 = time.time()
+    recipe = synth.RECIPES[args.workload]
+    g = synth.load_recipe_graph(args.workload)
+    log(f"graph {args.workload}: V={g.n_vertices} E={g.n_edges} ({time.time() - t0:.1f} s)")
+    G = fw.Graph.of(g)
+    info = G.info()
+    algo, prm, walk = recipe_params(fw, recipe)
+    L, seed = walk["length"], walk["seed"]
+    starts_np = synth.recipe_starts(args.workload, g)
+    n = starts_np.shape[0]
+    starts = torch.from_numpy(starts_np.view(np.int32)).to(dev)
+    out = torch.empty((n, L + 1), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    log(f"uploaded: {info['device_bytes'] / 1e9:.2f} GB; n={n} L={L} algo={algo}")
+
+    def run_pass(mode):
+        fw.walk(G, algo, prm, starts, L, seed, out=out, mode=mode, stream=stream, async_=True,
+                use_graph=bool(args.use_graph))
+
+    def timed(mode, steps, warmup):
+        for _ in range(warmup):
+            run_pass(mode)
+        fw.sync(G, stream)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        t_start = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            run_pass(mode)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        fw.sync(G, stream)
+        kern_ms = [a.elapsed_time(b) for a, b in evs]
+        return wall * 1e3 / steps, float(np.mean(kern_ms)), kern_ms
+
+    ms_step, kern_ms, all_ms = timed(args.mode, args.steps, args.warmup)
+    log(f"{args.mode}: {ms_step:.1f} ms/step, kernel {kern_ms:.1f} ms ({all_ms})")
+
+    deg = torch.from_numpy(np.diff(np.asarray(g.offsets)).astype(np.int64)).to(dev)
+    model = byte_model(algo, g.weights is not None, g.labels is not None)
+    hops, attempts, scanned, alg_bytes = account(torch, out, deg, model)
+    paths_main = out.clone()
+    value = hops / (ms_step / 1e3)
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    log(f"hops={hops} attempts={attempts} scanned={scanned} bytes={alg_bytes / 1e9:.1f} GB "
+        f"-> {value / 1e6:.1f} M steps/s, {achieved:.0f} GB/s algorithmic")
+
+    plain = None
+    if args.compare_plain and args.mode != "plain":
+        ms_p, kern_p, _ = timed("plain", max(1, min(args.steps, 2)), 0)
+        same = bool(torch.equal(out, paths_main))
+        plain = dict(ms_per_step=ms_p, value=hops / (ms_p / 1e3), identical_paths=same)
+        log(f"plain: {ms_p:.1f} ms/step, identical={same}")
+
+    traffic = None
+    tfile = ROOT / "profiles" / f"traffic_{args.workload}_{args.mode}.json"
+    if tfile.exists():
+        t = json.loads(tfile.read_text())
+        if t.get("kernel_source") == kernel_source_hash():
+            traffic = t.get("hbm_bytes_per_launch")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oprm = oracle_params(prm, algo)
+        host_paths = paths_main.cpu().numpy().view(np.uint32)
+        cpu = cpu_baseline(g, algo, oprm, starts_np, L, seed, n, args.cpu_seconds,
+                           lambda q: host_paths[q.astype(np.int64)])
+        log(f"cpu baseline: {cpu}")
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walk steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "mode": args.mode, "queries": n, "length": L,
+                   "n_vertices": g.n_vertices, "n_edges": g.n_edges,
+                   "max_degree": info["max_degree"]},
+        "hbm_gbps_algorithmic": achieved,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic},
+        "kernel_ms": kern_ms,
+        "hops": hops,
+        "attempted_hops": attempts,
+        "neighbours_scanned": scanned,
+        "edges_scanned_per_s": scanned / (kern_ms / 1e3),
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "plain": plain,
+        "cpu_baseline": cpu,
+        "latency": None,
+        "kernel_source": kernel_source_hash(),
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

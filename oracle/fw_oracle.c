@@ -110,7 +110,7 @@ int fwo_validate(const fwo_graph* g) {
     if (e < b || e > g->n_edges) return FWO_EINVAL;
     for (uint64_t i = b; i < e; ++i) {
       if (g->adj[i] >= g->n_vertices) return FWO_EINVAL;
-      if (i > b && g->adj[i] <= g->adj[i - 1]) return FWO_EINVAL;
+      if (i > b && g->adj[i] < g->adj[i - 1]) return FWO_EINVAL;
     }
   }
   return FWO_OK;

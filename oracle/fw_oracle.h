@@ -76,7 +76,8 @@ int fwo_node2vec_factors(uint32_t p_num, uint32_t p_den, uint32_t q_num, uint32_
                          fwo_params* out);
 
 /* Checks the CSR: offsets[0] = 0, monotone, offsets[V] = E, every id < V,
- * rows strictly ascending, V < 2^32 - 1. */
+ * rows ascending (a repeated id is a parallel edge, its own candidate),
+ * V < 2^32 - 1. */
 int fwo_validate(const fwo_graph* g);
 
 /* Transition weights of every neighbour of `cur` at hop t (prev is ignored at

@@ -1,0 +1,178 @@
+// Device primitives for the gfx950 walkers: the step draw (Philox4x64-10),
+// 64-bit scaling, wave64 integer scans and ballots, and the per-neighbour
+// transition-weight evaluators.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+constexpr uint32_t kEnd = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+
+enum Algo : int { kDeepWalk = 0, kNode2Vec = 1, kMetaPath = 2 };
+
+struct DevGraph {
+  const uint64_t* __restrict__ off;
+  const uint32_t* __restrict__ adj;
+  const uint32_t* __restrict__ w;    // nullptr: every weight is 1
+  const uint8_t* __restrict__ lab;   // nullptr: no labels
+  uint64_t nv;
+};
+
+struct DevParams {
+  uint32_t f_ret, f_in, f_out;
+  uint32_t schema_len;
+  uint8_t schema[16];
+};
+
+// ---------------------------------------------------------------------------
+// Step draw: word 0 of Philox4x64-10 (Salmon et al., SC 2011) at counter
+// (qid, t, 0, 0), key (seed, 0).  One draw per hop, no generator state.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint64_t qid, uint64_t t) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+  uint64_t c0 = qid, c1 = t, c2 = 0, c3 = 0, k0 = seed, k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t h0 = __umul64hi(kM0, c0), l0 = kM0 * c0;
+    const uint64_t h1 = __umul64hi(kM1, c2), l1 = kM1 * c2;
+    c0 = h1 ^ c1 ^ k0;
+    c1 = l1;
+    c2 = h0 ^ c3 ^ k1;
+    c3 = l0;
+    k0 += kW0;
+    k1 += kW1;
+  }
+  return c0;
+}
+
+// floor(u * total / 2^64) in [0, total).
+__device__ __forceinline__ uint64_t scale_draw(uint64_t u, uint64_t total) {
+  return __umul64hi(u, total);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 collectives built from DPP row shifts and row broadcasts.  They must
+// be called with every lane of the wavefront active.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  // Lanes whose source is outside the row, or whose row is masked off, read 0.
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = dpp32<CTRL, ROWS>((uint32_t)v);
+  const uint32_t hi = dpp32<CTRL, ROWS>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over the 64 lanes (Hillis-Steele inside each 16-lane
+// row, then row 0/2 totals into rows 1/3, then the rows 0-1 total into 2-3).
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+  x += dpp64<0x111, 0xF>(x);  // row_shr:1
+  x += dpp64<0x112, 0xF>(x);  // row_shr:2
+  x += dpp64<0x114, 0xF>(x);  // row_shr:4
+  x += dpp64<0x118, 0xF>(x);  // row_shr:8
+  x += dpp64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x) {
+  x += dpp32<0x111, 0xF>(x);
+  x += dpp32<0x112, 0xF>(x);
+  x += dpp32<0x114, 0xF>(x);
+  x += dpp32<0x118, 0xF>(x);
+  x += dpp32<0x142, 0xA>(x);
+  x += dpp32<0x143, 0xC>(x);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t readlane32(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) { return readlane64(wave_incl_scan(x), 63); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ int first_lane(uint64_t mask) { return (int)__builtin_ctzll(mask); }
+
+// ---------------------------------------------------------------------------
+// Transition weights (section 2.1).  One evaluator per hop; element i is the
+// i-th neighbour of the current vertex in CSR order.
+// ---------------------------------------------------------------------------
+// Lower-bound search of u in the sorted row adj[b, b + n).
+__device__ __forceinline__ bool row_contains(const uint32_t* __restrict__ adj, uint64_t b,
+                                             uint64_t n, uint32_t u) {
+  uint64_t lo = b, hi = b + n;
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (adj[mid] < u)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < b + n && adj[lo] == u;
+}
+
+template <int ALGO, bool WEIGHTED>
+struct Eval {
+  const uint32_t* __restrict__ adj;
+  const uint32_t* __restrict__ w;
+  const uint8_t* __restrict__ lab;
+  uint64_t o;  // first CSR entry of the current vertex
+  // node2vec: previous vertex, its row, the factors; first hop uses w alone.
+  uint32_t prev;
+  uint64_t po, pd;
+  uint32_t f_ret, f_in, f_out;
+  bool first;
+  // MetaPath: label this hop must carry.
+  uint32_t want;
+
+  __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
+    const uint64_t e = o + i;
+    const uint64_t wt = WEIGHTED ? (uint64_t)w[e] : 1ull;
+    if (ALGO == kNode2Vec) {
+      if (first) return wt;
+      const uint32_t u = adj[e];
+      uint32_t f;
+      if (u == prev)
+        f = f_ret;
+      else if (row_contains(adj, po, pd, u))
+        f = f_in;
+      else
+        f = f_out;
+      return wt * f;
+    } else if (ALGO == kMetaPath) {
+      return lab[e] == want ? wt : 0ull;
+    } else {
+      return wt;
+    }
+  }
+};
+
+}  // namespace fw

@@ -1,0 +1,43 @@
+// Internal host-side state shared by the runtime's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+
+#include "flowwalk.h"
+#include "fw_kernels.h"
+
+struct fw_graph {
+  uint64_t nv = 0, ne = 0, max_deg = 0, max_w = 1;
+  uint64_t* d_off = nullptr;
+  uint32_t* d_adj = nullptr;
+  uint32_t* d_w = nullptr;
+  uint8_t* d_lab = nullptr;
+  uint32_t* d_status = nullptr;  // sticky error bits written by kernels
+  uint64_t* d_head = nullptr;    // global task-pool head of the persistent form
+  int device = 0;
+  int num_cus = 0;
+  uint64_t bytes = 0;
+  mutable std::mutex mu;                           // guards the caches below
+  mutable std::map<int, fw::TuneCfg> tuned;        // per algorithm
+  mutable void* graph_cache = nullptr;             // captured launch graphs
+};
+
+namespace fw {
+
+int set_error(int code, const char* msg);
+int check_walk_args(const fw_graph* g, int algo, const fw_params* params, uint64_t n,
+                    uint32_t length, const void* starts, const void* out, DevParams* dp);
+DevGraph dev_graph(const fw_graph* g);
+int read_status(const fw_graph* g, hipStream_t stream);
+
+// Persistent form: configuration and launch (fw_persistent_host.hip).
+int resolve_tune(const fw_graph* g, int algo, const fw_tune* user, TuneCfg* cfg);
+hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hipStream_t stream,
+                                     bool use_graph);
+void release_graph_state(fw_graph* g);
+
+}  // namespace fw

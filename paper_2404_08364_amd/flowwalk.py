@@ -1,0 +1,220 @@
+"""Python binding of libflowwalk.so (argument marshalling only).
+
+Every hop of every walk runs in the library's HIP kernels; this module only
+converts arguments.  PyTorch supplies device memory and streams: ``starts``
+and ``out`` are CUDA (HIP) tensors.  There is no CPU fallback: if the native
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libflowwalk.so"
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EHIP, ECANCELED = 0, -1, -2, -3, -4, -5
+DEEPWALK, NODE2VEC, METAPATH = 0, 1, 2
+ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH}
+MODES = {"auto": 0, "plain": 1, "persistent": 2}
+END = 0xFFFFFFFF
+
+if not LIB_PATH.exists():
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2404_08364_amd.build` "
+        "(hipcc, gfx950); there is no fallback path")
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_uint64), ("n_edges", ctypes.c_uint64),
+                ("offsets", ctypes.c_void_p), ("adj", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("f_ret", ctypes.c_uint32), ("f_in", ctypes.c_uint32),
+                ("f_out", ctypes.c_uint32), ("schema_len", ctypes.c_uint32),
+                ("schema", ctypes.c_uint8 * 16)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_uint64), ("n_edges", ctypes.c_uint64),
+                ("max_degree", ctypes.c_uint64), ("max_weight", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("weighted", ctypes.c_int),
+                ("labelled", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("tiny_max", ctypes.c_uint32), ("hub_min", ctypes.c_uint32),
+                ("wgs_per_cu", ctypes.c_uint32), ("fetch", ctypes.c_uint32)]
+
+
+class WalkOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("stream", ctypes.c_void_p), ("async_", ctypes.c_int),
+                ("qid_base", ctypes.c_uint64), ("tune", ctypes.POINTER(Tune)),
+                ("use_graph", ctypes.c_int)]
+
+
+def _bind(lib):
+    u64, u32, i32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
+    sig = {
+        "fw_graph_upload": ([ctypes.POINTER(Csr), vp, vp, ctypes.POINTER(vp)], i32),
+        "fw_graph_free": ([vp], i32),
+        "fw_graph_info_get": ([vp, ctypes.POINTER(GraphInfo)], i32),
+        "fw_node2vec_factors": ([u32, u32, u32, u32, ctypes.POINTER(Params)], i32),
+        "fw_walk": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp], i32),
+        "fw_walk_ex": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
+                        ctypes.POINTER(WalkOpts)], i32),
+        "fw_sync": ([vp, vp], i32),
+        "fw_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _bind(ctypes.CDLL(str(LIB_PATH)))
+
+
+def lib():
+    return _lib
+
+
+class FWError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.fw_last_error().decode(errors="replace")
+        super().__init__(f"{what}: status {status}: {msg}")
+        self.status = status
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise FWError(rc, what)
+
+
+def node2vec_factors(p_num: int, p_den: int, q_num: int, q_den: int) -> tuple[int, int, int]:
+    out = Params()
+    _check(_lib.fw_node2vec_factors(p_num, p_den, q_num, q_den, ctypes.byref(out)),
+           "fw_node2vec_factors")
+    return out.f_ret, out.f_in, out.f_out
+
+
+def make_params(factors=(1, 1, 1), schema=()) -> Params:
+    p = Params()
+    p.f_ret, p.f_in, p.f_out = factors
+    p.schema_len = len(schema)
+    for i, s in enumerate(schema):
+        p.schema[i] = s
+    return p
+
+
+def make_tune(**kw) -> Tune:
+    t = Tune()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+class Graph:
+    """A CSR graph resident in HBM (owned by the library)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def upload(cls, offsets, adj, weights=None, labels=None) -> "Graph":
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        a = np.ascontiguousarray(adj, dtype=np.uint32)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint32)
+        lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint8)
+        csr = Csr(off.shape[0] - 1, a.shape[0], off.ctypes.data, a.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(_lib.fw_graph_upload(ctypes.byref(csr), None if w is None else w.ctypes.data,
+                                    None if lab is None else lab.ctypes.data, ctypes.byref(h)),
+               "fw_graph_upload")
+        return cls(h.value)
+
+    @classmethod
+    def of(cls, g) -> "Graph":
+        """Uploads any object with offsets/adj/weights/labels arrays."""
+        return cls.upload(g.offsets, g.adj, getattr(g, "weights", None),
+                          getattr(g, "labels", None))
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None or not self._h.value:
+            raise ValueError("graph was freed")
+        return self._h
+
+    def info(self) -> dict:
+        gi = GraphInfo()
+        _check(_lib.fw_graph_info_get(self.handle, ctypes.byref(gi)), "fw_graph_info_get")
+        return {k: getattr(gi, k) for k, _ in GraphInfo._fields_}
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.fw_graph_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def walk_ptr(graph: Graph, algo, prm: Params | None, starts_ptr: int, n: int, length: int,
+             seed: int, out_ptr: int, mode="auto", stream=None, async_=False, qid_base=0,
+             tune: Tune | None = None, use_graph=False) -> int:
+    """Raw-pointer form of fw_walk_ex; returns the status."""
+    o = WalkOpts()
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.stream = _stream_handle(stream)
+    o.async_ = int(bool(async_))
+    o.qid_base = qid_base
+    o.tune = ctypes.pointer(tune) if tune is not None else None
+    o.use_graph = int(bool(use_graph))
+    a = ALGOS.get(algo, algo)
+    return _lib.fw_walk_ex(graph.handle, a, None if prm is None else ctypes.byref(prm),
+                           starts_ptr, n, length, seed, out_ptr, ctypes.byref(o))
+
+
+def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int, out=None,
+         mode="auto", stream=None, async_=False, qid_base=0, tune: Tune | None = None,
+         use_graph=False):
+    """Runs len(starts) queries; returns the int32 tensor [n, length + 1]
+    (FW_END reads as -1)."""
+    import torch
+    if starts.device.type != "cuda":
+        raise ValueError("starts must be a device tensor")
+    if starts.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("starts must be int32 or uint32")
+    starts = starts.contiguous()
+    n = starts.shape[0]
+    if out is None:
+        out = torch.empty((n, length + 1), dtype=torch.int32, device=starts.device)
+    if out.dtype not in (torch.int32, torch.uint32) or not out.is_contiguous() \
+            or out.numel() != n * (length + 1):
+        raise ValueError("out must be a contiguous int32 tensor of n * (length + 1) entries")
+    if stream is None:
+        stream = torch.cuda.current_stream(starts.device)
+    rc = walk_ptr(graph, algo, prm, starts.data_ptr(), n, length, seed, out.data_ptr(), mode,
+                  stream, async_, qid_base, tune, use_graph)
+    _check(rc, "fw_walk_ex")
+    return out
+
+
+def sync(graph: Graph, stream=None):
+    _check(_lib.fw_sync(graph.handle, _stream_handle(stream)), "fw_sync")
