@@ -139,7 +139,9 @@ typedef struct fw_tune {
   uint32_t tiny_max;     /* degree <= tiny_max: sub-wave sampler */
   uint32_t hub_min;      /* degree >= hub_min: whole-workgroup sampler */
   uint32_t wgs_per_cu;   /* persistent workgroups per compute unit */
-  uint32_t fetch;        /* queries claimed per atomic fetch */
+  uint32_t fetch;        /* reserved, 0 */
+  uint32_t hash_cells;   /* LDS cells per workgroup for the node2vec
+                            membership hash set (power of two) */
 } fw_tune;
 
 typedef struct fw_walk_opts {

@@ -13,7 +13,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libflowwalk.so"
-SOURCES = ["fw_runtime.hip", "fw_plain.hip", "fw_persistent_host.hip"]
+SOURCES = ["fw_runtime.hip", "fw_plain.hip", "fw_persistent.hip", "fw_persistent_host.hip"]
 ARCH = os.environ.get("FW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

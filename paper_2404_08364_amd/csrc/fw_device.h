@@ -139,15 +139,23 @@ __device__ __forceinline__ bool row_contains(const uint32_t* __restrict__ adj, u
   return lo < b + n && adj[lo] == u;
 }
 
-template <int ALGO, bool WEIGHTED>
+// Membership in N(prev) by binary search of its sorted row in global memory.
+struct MemberGlobal {
+  const uint32_t* __restrict__ adj;
+  uint64_t po, pd;
+  __device__ __forceinline__ bool contains(uint32_t u) const { return row_contains(adj, po, pd, u); }
+};
+
+template <int ALGO, bool WEIGHTED, class MEM = MemberGlobal>
 struct Eval {
   const uint32_t* __restrict__ adj;
   const uint32_t* __restrict__ w;
   const uint8_t* __restrict__ lab;
   uint64_t o;  // first CSR entry of the current vertex
-  // node2vec: previous vertex, its row, the factors; first hop uses w alone.
+  // node2vec: previous vertex, membership in its row, the factors; the
+  // first hop uses w alone.
   uint32_t prev;
-  uint64_t po, pd;
+  MEM mem;
   uint32_t f_ret, f_in, f_out;
   bool first;
   // MetaPath: label this hop must carry.
@@ -162,7 +170,7 @@ struct Eval {
       uint32_t f;
       if (u == prev)
         f = f_ret;
-      else if (row_contains(adj, po, pd, u))
+      else if (mem.contains(u))
         f = f_in;
       else
         f = f_out;
@@ -171,6 +179,38 @@ struct Eval {
       return lab[e] == want ? wt : 0ull;
     } else {
       return wt;
+    }
+  }
+
+  // Weights of the four entries at absolute CSR positions [p, p + 4), p a
+  // multiple of 4 (the arrays are padded so that a quad never ends past the
+  // allocation).  Entries outside the current slice are masked by the caller.
+  __device__ __forceinline__ void quad(uint64_t p, uint64_t out[4]) const {
+    uint32_t wq[4] = {1u, 1u, 1u, 1u};
+    if (WEIGHTED) {
+      const uint4 v = *reinterpret_cast<const uint4*>(w + p);
+      wq[0] = v.x; wq[1] = v.y; wq[2] = v.z; wq[3] = v.w;
+    }
+    if (ALGO == kNode2Vec) {
+      if (first) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[j] = wq[j];
+        return;
+      }
+      const uint4 a = *reinterpret_cast<const uint4*>(adj + p);
+      const uint32_t u[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t f = (u[j] == prev) ? f_ret : (mem.contains(u[j]) ? f_in : f_out);
+        out[j] = (uint64_t)wq[j] * f;
+      }
+    } else if (ALGO == kMetaPath) {
+      const uint32_t l = *reinterpret_cast<const uint32_t*>(lab + p);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[j] = (((l >> (8 * j)) & 0xFFu) == want) ? wq[j] : 0ull;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[j] = wq[j];
     }
   }
 };

@@ -14,7 +14,8 @@ struct TuneCfg {
   uint32_t tiny_max;    // degree <= tiny_max: sub-wave sampler
   uint32_t hub_min;     // degree >= hub_min: workgroup sampler
   uint32_t wgs_per_cu;  // persistent workgroups per CU
-  uint32_t fetch;       // queries claimed per atomic fetch
+  uint32_t fetch;       // reserved (refills claim every empty slot at once)
+  uint32_t hash_cells;  // LDS hash-set cells per workgroup (power of two)
 };
 
 struct LaunchArgs {

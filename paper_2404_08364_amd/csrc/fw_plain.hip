@@ -66,11 +66,12 @@ __global__ __launch_bounds__(256) void k_walk_plain(DevGraph g, DevParams prm,
         ev.f_ret = prm.f_ret;
         ev.f_in = prm.f_in;
         ev.f_out = prm.f_out;
+        ev.mem.adj = g.adj;
         if (t > 0) {
-          ev.po = g.off[prev];
-          ev.pd = g.off[prev + 1] - ev.po;
+          ev.mem.po = g.off[prev];
+          ev.mem.pd = g.off[prev + 1] - ev.mem.po;
         } else {
-          ev.po = ev.pd = 0;
+          ev.mem.po = ev.mem.pd = 0;
         }
       }
       if (ALGO == kMetaPath) ev.want = prm.schema[t % prm.schema_len];
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void k_walk_plain(DevGraph g, DevParams prm,
         // All weights 1: the prefix sum at i is i + 1, so the pick is r.
         idx = d ? (int64_t)scale_draw(u, d) : -1;
       } else {
-        idx = wave_pick(ev, d, u);
+        idx = wave_pick(ev, o, d, u);
       }
       if (idx < 0) break;
       const uint32_t nxt = uniform32(g.adj[o + (uint64_t)idx]);

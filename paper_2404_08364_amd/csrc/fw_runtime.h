@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 
@@ -17,16 +18,23 @@ struct fw_graph {
   uint32_t* d_w = nullptr;
   uint8_t* d_lab = nullptr;
   uint32_t* d_status = nullptr;  // sticky error bits written by kernels
-  uint64_t* d_head = nullptr;    // global task-pool head of the persistent form
+  uint64_t* d_head = nullptr;    // kHeadSlots task-pool heads, one per in-flight launch
   int device = 0;
   int num_cus = 0;
+  size_t lds_per_block = 0;                        // device limit, bytes
   uint64_t bytes = 0;
+  mutable std::atomic<uint64_t> launches{0};       // rotates the head counters
   mutable std::mutex mu;                           // guards the caches below
   mutable std::map<int, fw::TuneCfg> tuned;        // per algorithm
   mutable void* graph_cache = nullptr;             // captured launch graphs
 };
 
 namespace fw {
+
+// Head counters (128 B apart) rotated over launches so that up to this many
+// persistent launches on one graph may be in flight on different streams.
+constexpr int kHeadSlots = 64;
+constexpr int kHeadStride = 16;
 
 int set_error(int code, const char* msg);
 int check_walk_args(const fw_graph* g, int algo, const fw_params* params, uint64_t n,

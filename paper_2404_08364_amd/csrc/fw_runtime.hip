@@ -191,23 +191,32 @@ int fw_graph_upload(const fw_csr* csr, const uint32_t* weights, const uint8_t* l
     return hip_fail(e, "querying the device");
   }
   g->num_cus = prop.multiProcessorCount;
+  g->lds_per_block = prop.sharedMemPerBlock;
   auto alloc = [&](void** p, size_t bytes) -> hipError_t {
     g->bytes += bytes;
     return hipMalloc(p, bytes ? bytes : 4);
   };
+  // Per-edge arrays get kPad zeroed entries past the end: the kernels read
+  // whole 16-byte quads, which may reach up to 3 entries beyond entry E - 1.
+  constexpr uint64_t kPad = 16;
   e = alloc((void**)&g->d_off, (nv + 1) * sizeof(uint64_t));
-  if (e == hipSuccess) e = alloc((void**)&g->d_adj, ne * sizeof(uint32_t));
-  if (e == hipSuccess && weights) e = alloc((void**)&g->d_w, ne * sizeof(uint32_t));
-  if (e == hipSuccess && labels) e = alloc((void**)&g->d_lab, ne);
+  if (e == hipSuccess) e = alloc((void**)&g->d_adj, (ne + kPad) * sizeof(uint32_t));
+  if (e == hipSuccess && weights) e = alloc((void**)&g->d_w, (ne + kPad) * sizeof(uint32_t));
+  if (e == hipSuccess && labels) e = alloc((void**)&g->d_lab, ne + kPad);
+  if (e == hipSuccess) e = hipMemset(g->d_adj + ne, 0, kPad * sizeof(uint32_t));
+  if (e == hipSuccess && weights) e = hipMemset(g->d_w + ne, 0, kPad * sizeof(uint32_t));
+  if (e == hipSuccess && labels) e = hipMemset(g->d_lab + ne, 0, kPad);
   if (e == hipSuccess) e = alloc((void**)&g->d_status, 256);
-  if (e == hipSuccess) e = alloc((void**)&g->d_head, 256);
+  if (e == hipSuccess)
+    e = alloc((void**)&g->d_head, fw::kHeadSlots * fw::kHeadStride * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMemcpy(g->d_off, off, (nv + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && ne) e = hipMemcpy(g->d_adj, adj, ne * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && weights && ne)
     e = hipMemcpy(g->d_w, weights, ne * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && labels && ne) e = hipMemcpy(g->d_lab, labels, ne, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(g->d_status, 0, 256);
-  if (e == hipSuccess) e = hipMemset(g->d_head, 0, 256);
+  if (e == hipSuccess)
+    e = hipMemset(g->d_head, 0, fw::kHeadSlots * fw::kHeadStride * sizeof(uint64_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(FW_ENOMEM, "device allocation")
@@ -266,7 +275,7 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
   a.qid_base = o.qid_base;
   a.out = out_paths;
   a.status = g->d_status;
-  a.head = g->d_head;
+  a.head = g->d_head + fw::kHeadStride * (g->launches.fetch_add(1) % fw::kHeadSlots);
   a.num_cus = g->num_cus;
   hipError_t e;
   if (o.mode == FW_MODE_PLAIN) {

@@ -1,63 +1,141 @@
-// One-wavefront sampler for a hop of any degree.
+// One-wavefront sampler for a hop of any degree, over 16-byte quads.
 //
-// It computes the pick of the exact inverse CDF without any buffer: the
-// neighbour slice is split into at most 64 contiguous groups; one streaming
-// pass (coalesced, lane j reads element j of each 64-wide chunk) leaves the
-// total of group g in lane g; a wave prefix scan of those totals gives T, the
-// draw r, and the group holding r; the same step then repeats inside that
-// group until at most 64 elements remain, where an inclusive scan and a
-// ballot give the index.  Each level re-reads 1/64 of the previous one, so a
-// hop of degree d evaluates about d * 64/63 transition weights.
+// The neighbour slice [o, o + d) of the CSR arrays is read as aligned quads of
+// four entries (one dwordx4 load per array per lane): quad q covers absolute
+// positions [A + 4q, A + 4q + 4) with A = o rounded down to a multiple of 4;
+// positions outside the slice weigh 0.  The pick of the exact inverse CDF is
+// found without any buffer: the quads are split into at most 64 contiguous
+// groups; one streaming pass (lane j reads quad j of each 64-quad chunk)
+// leaves the total of group g in lane g; a wave prefix scan of those totals
+// gives T, the draw r and the group holding r; the same step repeats inside
+// that group until at most 64 quads remain, where a scan over the lanes and a
+// ballot give the quad and a scan inside the quad gives the entry.  Each
+// level re-reads 1/64 of the previous one.
 #pragma once
 
 #include "fw_device.h"
 
 namespace fw {
 
-// Returns the index (relative to the slice) of the picked neighbour, or -1
-// when the slice's total weight is 0.  d and u are wave-uniform.
+// Absolute-position view of a slice.
+struct QuadSlice {
+  uint64_t o, d;   // first entry, degree
+  uint64_t a;      // o rounded down to a multiple of 4
+  uint64_t nq;     // quads covering [o, o + d)
+  __device__ __forceinline__ QuadSlice(uint64_t o_, uint64_t d_) : o(o_), d(d_) {
+    a = o_ & ~3ull;
+    nq = d_ ? (o_ + d_ - a + 3) / 4 : 0;
+  }
+};
+
+// The four transition weights of quad q (0 outside the slice).
 template <class E>
-__device__ __forceinline__ int64_t wave_pick(const E& ev, uint64_t d, uint64_t u) {
-  const int lane = lane_id();
-  uint64_t lo = 0, len = d, r = 0;
-  bool have_r = false;
-  while (len > kWave) {
+__device__ __forceinline__ void quad_weights(const E& ev, const QuadSlice& s, uint64_t q,
+                                             uint64_t w[4]) {
+  const uint64_t p = s.a + 4 * q;
+  ev.quad(p, w);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (p + j < s.o || p + j >= s.o + s.d) w[j] = 0;
+}
+
+// Group layout of `len` quads: at most 64 groups of per_group 64-quad chunks.
+struct GroupSplit {
+  uint64_t gsz, groups;
+  __device__ __forceinline__ explicit GroupSplit(uint64_t len) {
     const uint64_t chunks = (len + kWave - 1) / kWave;
-    const uint64_t per_group = (chunks + kWave - 1) / kWave;  // chunks per group
-    const uint64_t gsz = per_group * kWave;
-    const uint64_t groups = (len + gsz - 1) / gsz;
-    uint64_t mine = 0;  // lane g: total of group g
-    for (uint64_t g = 0; g < groups; ++g) {
-      const uint64_t gb = lo + g * gsz;
-      const uint64_t ge = min(gb + gsz, lo + len);
-      uint64_t acc = 0;
-      for (uint64_t i = gb + lane; i < ge; i += kWave) acc += ev(i);
-      const uint64_t tot = wave_sum(acc);
-      if ((uint64_t)lane == g) mine = tot;
+    const uint64_t per_group = (chunks + kWave - 1) / kWave;
+    gsz = per_group * kWave;
+    groups = gsz ? (len + gsz - 1) / gsz : 0;
+  }
+};
+
+// Lane g returns the total of group g of quads [lo, lo + len).
+template <class E>
+__device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSlice& s,
+                                                      uint64_t lo, uint64_t len,
+                                                      const GroupSplit& sp) {
+  const int lane = lane_id();
+  uint64_t mine = 0;
+  for (uint64_t g = 0; g < sp.groups; ++g) {
+    const uint64_t gb = lo + g * sp.gsz;
+    const uint64_t ge = min(gb + sp.gsz, lo + len);
+    uint64_t acc = 0;
+#pragma unroll 2
+    for (uint64_t q = gb + lane; q < ge; q += kWave) {
+      uint64_t w[4];
+      quad_weights(ev, s, q, w);
+      acc += (w[0] + w[1]) + (w[2] + w[3]);
     }
+    const uint64_t tot = wave_sum(acc);
+    if ((uint64_t)lane == g) mine = tot;
+  }
+  return mine;
+}
+
+// Given r below the total of quads [lo, lo + len), returns the relative index
+// (from s.o) of the first entry whose inclusive prefix (from quad lo) exceeds r.
+template <class E>
+__device__ __forceinline__ uint64_t wave_locate(const E& ev, const QuadSlice& s, uint64_t lo,
+                                                uint64_t len, uint64_t r) {
+  const int lane = lane_id();
+  while (len > kWave) {
+    const GroupSplit sp(len);
+    const uint64_t mine = wave_group_totals(ev, s, lo, len, sp);
     const uint64_t incl = wave_incl_scan(mine);
-    if (!have_r) {
-      const uint64_t total = readlane64(incl, kWave - 1);
-      if (total == 0) return -1;
-      r = scale_draw(u, total);
-      have_r = true;
-    }
     // incl(63) > r always holds; the fallback only keeps indices in range.
     const uint64_t m = ballot(incl > r);
-    const int gs = m ? first_lane(m) : (int)groups - 1;
+    const int gs = m ? first_lane(m) : (int)sp.groups - 1;
     r -= readlane64(incl - mine, gs);
-    lo += (uint64_t)gs * gsz;
-    len = min(gsz, len - (uint64_t)gs * gsz);
+    lo += (uint64_t)gs * sp.gsz;
+    len = min(sp.gsz, len - (uint64_t)gs * sp.gsz);
   }
-  const uint64_t v = (uint64_t)lane < len ? ev(lo + lane) : 0ull;
-  const uint64_t incl = wave_incl_scan(v);
-  if (!have_r) {
+  uint64_t w[4] = {0, 0, 0, 0};
+  if ((uint64_t)lane < len) quad_weights(ev, s, lo + lane, w);
+  const uint64_t c0 = w[0], c1 = c0 + w[1], c2 = c1 + w[2], tot = c2 + w[3];
+  const uint64_t incl = wave_incl_scan(tot);
+  const uint64_t excl = incl - tot;
+  const uint64_t m = ballot(incl > r);
+  const int L = m ? first_lane(m) : (int)len - 1;
+  const uint64_t rr = r - excl;  // meaningful in lane L
+  const uint32_t j = rr < c0 ? 0u : rr < c1 ? 1u : rr < c2 ? 2u : 3u;
+  const uint32_t jl = readlane32(j, L);
+  return s.a + 4 * (lo + (uint64_t)L) + jl - s.o;
+}
+
+// Returns the index (relative to the slice) of the picked neighbour, or -1
+// when the slice's total weight is 0.  o, d and u are wave-uniform.
+template <class E>
+__device__ __forceinline__ int64_t wave_pick(const E& ev, uint64_t o, uint64_t d, uint64_t u) {
+  const QuadSlice s(o, d);
+  const int lane = lane_id();
+  if (s.nq > (uint64_t)kWave) {
+    const GroupSplit sp(s.nq);
+    const uint64_t mine = wave_group_totals(ev, s, 0, s.nq, sp);
+    const uint64_t incl = wave_incl_scan(mine);
     const uint64_t total = readlane64(incl, kWave - 1);
     if (total == 0) return -1;
-    r = scale_draw(u, total);
+    uint64_t r = scale_draw(u, total);
+    const uint64_t m = ballot(incl > r);
+    const int gs = m ? first_lane(m) : (int)sp.groups - 1;
+    r -= readlane64(incl - mine, gs);
+    const uint64_t lo = (uint64_t)gs * sp.gsz;
+    return (int64_t)wave_locate(ev, s, lo, min(sp.gsz, s.nq - lo), r);
   }
+  uint64_t w[4] = {0, 0, 0, 0};
+  if ((uint64_t)lane < s.nq) quad_weights(ev, s, lane, w);
+  const uint64_t c0 = w[0], c1 = c0 + w[1], c2 = c1 + w[2], tot = c2 + w[3];
+  const uint64_t incl = wave_incl_scan(tot);
+  const uint64_t total = readlane64(incl, kWave - 1);
+  if (total == 0) return -1;
+  const uint64_t r = scale_draw(u, total);
+  const uint64_t excl = incl - tot;
   const uint64_t m = ballot(incl > r);
-  return (int64_t)(lo + (m ? (uint64_t)first_lane(m) : len - 1));
+  const int L = m ? first_lane(m) : (int)s.nq - 1;
+  const uint64_t rr = r - excl;
+  const uint32_t j = rr < c0 ? 0u : rr < c1 ? 1u : rr < c2 ? 2u : 3u;
+  const uint32_t jl = readlane32(j, L);
+  return (int64_t)(s.a + 4 * (uint64_t)L + jl - s.o);
 }
 
 }  // namespace fw

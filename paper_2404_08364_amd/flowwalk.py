@@ -48,7 +48,8 @@ class GraphInfo(ctypes.Structure):
 class Tune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_uint32), ("slots", ctypes.c_uint32),
                 ("tiny_max", ctypes.c_uint32), ("hub_min", ctypes.c_uint32),
-                ("wgs_per_cu", ctypes.c_uint32), ("fetch", ctypes.c_uint32)]
+                ("wgs_per_cu", ctypes.c_uint32), ("fetch", ctypes.c_uint32),
+                ("hash_cells", ctypes.c_uint32)]
 
 
 class WalkOpts(ctypes.Structure):

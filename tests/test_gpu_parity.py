@@ -131,3 +131,77 @@ def test_errors(env):
     empty = torch.empty(0, dtype=torch.int32, device="cuda")
     out = fw.walk(G, "deepwalk", None, empty, 3, 1)
     assert out.shape == (0, 4)
+
+
+TUNES = [
+    dict(wg_size=256, slots=1, tiny_max=1, hub_min=2, wgs_per_cu=1, hash_cells=256),
+    dict(wg_size=256, slots=7, tiny_max=4, hub_min=65, wgs_per_cu=3, hash_cells=256),
+    dict(wg_size=512, slots=64, tiny_max=16, hub_min=2048, wgs_per_cu=2, hash_cells=8192),
+    dict(wg_size=1024, slots=128, tiny_max=16, hub_min=300, wgs_per_cu=1, hash_cells=16384),
+    dict(wg_size=512, slots=33, tiny_max=8, hub_min=100000, wgs_per_cu=4, hash_cells=512),
+]
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=lambda t: "wg{wg_size}-s{slots}-tm{tiny_max}-hm{hub_min}-h{hash_cells}".format(**t))
+@pytest.mark.parametrize("algo,factors,schema", ALGOS[:3] + ALGOS[3:4])
+def test_persistent_tunes(env, powerlaw, tune, algo, factors, schema):
+    """Every launch configuration of the persistent form gives the oracle's
+    walks (degree classes, pool sizes, hash-set capacity that forces the
+    global-search fallback)."""
+    torch, fw = env
+    g = powerlaw
+    starts = np.arange(g.n_vertices, dtype=np.uint32)[::7]
+    _check(env, g, algo, factors, schema, starts, 10, 4242, "persistent",
+           tune=fw.make_tune(**tune))
+
+
+def test_persistent_star_hubs_with_tunes(env):
+    torch, fw = env
+    g = _star(70_000, 3)
+    starts = np.concatenate([np.zeros(40, np.uint32), np.arange(1, 300, dtype=np.uint32)])
+    for tune in TUNES:
+        _check(env, g, "node2vec", (2, 3, 5), (), starts, 7, 99, "persistent",
+               tune=fw.make_tune(**tune))
+
+
+def test_graph_replay_matches_eager(env, powerlaw):
+    """The captured hipGraph of the persistent launch replays to the same
+    walks every time, with eager work and synchronisation in between."""
+    torch, fw = env
+    g = powerlaw
+    G = fw.Graph.of(g)
+    prm = fw.make_params((1, 2, 4))
+    starts = torch.arange(0, g.n_vertices, 3, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    eager = fw.walk(G, "node2vec", prm, starts, 15, 77, mode="persistent")
+    torch.cuda.synchronize()
+    out = torch.empty_like(eager)
+    for i in range(4):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            fw.walk(G, "node2vec", prm, starts, 15, 77, out=out, mode="persistent",
+                    stream=stream, use_graph=True)
+        stream.synchronize()
+        assert torch.equal(out, eager), f"replay {i}"
+        junk = fw.walk(G, "deepwalk", None, starts[:100], 3, i, mode="plain")
+        torch.cuda.synchronize()
+        del junk
+    exp = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts.cpu().numpy(), 15, 77)
+    assert_rows_equal(out.cpu().numpy().view(np.uint32), exp, "graph replay")
+
+
+def test_async_on_stream_and_qid_base(env, powerlaw):
+    torch, fw = env
+    g = powerlaw
+    G = fw.Graph.of(g)
+    starts = np.arange(g.n_vertices, dtype=np.uint32)[::11]
+    st = torch.from_numpy(starts.astype(np.int32)).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = fw.walk(G, "metapath", fw.make_params(schema=[2, 0]), st, 9, 5, mode="persistent",
+                      stream=s, async_=True, qid_base=123456789)
+    fw.sync(G, s)
+    exp = oracle.walk(g, "metapath", oracle.params(schema=[2, 0]), starts, 9, 5,
+                      qid_base=123456789)
+    assert_rows_equal(out.cpu().numpy().view(np.uint32), exp, "async qid_base")
