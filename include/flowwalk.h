@@ -125,23 +125,36 @@ int fw_walk(const fw_graph* g, fw_algo algo, const fw_params* params, const uint
 /* Kernel choice for fw_walk_ex.
  *   FW_MODE_PLAIN       one wavefront per query, queries assigned statically
  *                       (no load balancing: the baseline).
- *   FW_MODE_PERSISTENT  persistent workgroups with a local slot pool refilled
- *                       from a global atomic head (dynamic scheduling,
- *                       section 5.2), degree-class samplers (sub-wave, wave,
- *                       whole workgroup; section 5.1).
- *   FW_MODE_AUTO        the persistent form with the tuned configuration. */
-typedef enum { FW_MODE_AUTO = 0, FW_MODE_PLAIN = 1, FW_MODE_PERSISTENT = 2 } fw_mode;
+ *   FW_MODE_PERSISTENT  persistent wavefronts that claim queries from a
+ *                       global atomic head (dynamic scheduling, section 5.2);
+ *                       each keeps four queries, batches tiny-degree hops
+ *                       four to a wavefront and runs the others on the whole
+ *                       wavefront (sampler organisation of section 5.1).
+ *   FW_MODE_AUTO        FW_MODE_PERSISTENT with the tuned configuration.
+ *   FW_MODE_STAGED      the paper's two-stage block design on wave64:
+ *                       persistent workgroups with an LDS task pool, wave
+ *                       samplers, then a whole-workgroup sampler for hubs. */
+typedef enum {
+  FW_MODE_AUTO = 0,
+  FW_MODE_PLAIN = 1,
+  FW_MODE_PERSISTENT = 2,
+  FW_MODE_STAGED = 3
+} fw_mode;
 
-/* Launch configuration of the persistent form (0 in any field = default). */
+/* Launch configuration of the persistent and staged forms (0 in any field =
+ * the tuned or default value).
+ *   persistent: tiny_max, wgs_per_cu (256-thread workgroups per CU),
+ *               hash_cells (LDS cells per wavefront, power of two >= 64);
+ *   staged:     wg_size, slots, tiny_max, hub_min, wgs_per_cu,
+ *               hash_cells (LDS cells per workgroup). */
 typedef struct fw_tune {
-  uint32_t wg_size;      /* threads per workgroup: 256, 512 or 1024 */
-  uint32_t slots;        /* local task-pool slots per workgroup, <= 256 */
-  uint32_t tiny_max;     /* degree <= tiny_max: sub-wave sampler */
-  uint32_t hub_min;      /* degree >= hub_min: whole-workgroup sampler */
-  uint32_t wgs_per_cu;   /* persistent workgroups per compute unit */
+  uint32_t wg_size;      /* staged: threads per workgroup, 256/512/1024 */
+  uint32_t slots;        /* staged: local task-pool slots, <= 128 */
+  uint32_t tiny_max;     /* degree <= tiny_max (<= 16): sub-wave sampler */
+  uint32_t hub_min;      /* staged: degree >= hub_min: workgroup sampler */
+  uint32_t wgs_per_cu;   /* resident workgroups per compute unit */
   uint32_t fetch;        /* reserved, 0 */
-  uint32_t hash_cells;   /* LDS cells per workgroup for the node2vec
-                            membership hash set (power of two) */
+  uint32_t hash_cells;   /* LDS cells for the node2vec membership structure */
 } fw_tune;
 
 typedef struct fw_walk_opts {
@@ -165,6 +178,59 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
  * status that kernels of graph g detected since the last check (FW_EINVAL
  * for a start vertex >= V), clearing it. */
 int fw_sync(const fw_graph* g, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Served form: continuous batching of walk requests (graph and in-flight
+ * walks resident in HBM).  Requests are admitted in arrival order while
+ * their device memory, n * 4 + n * (length + 1) * 4 bytes (rounded up to 256),
+ * fits in mem_budget_bytes (the per-request form of Eq. 5's rule that
+ * result memory bounds the batch, section 5.2).  Admitted requests run as
+ * multi-request persistent launches on up to max_inflight streams at once,
+ * so work that arrives while other work is on the GPU joins it there.  A
+ * request's walks equal fw_walk's on the same starts and seed (query i of
+ * the request has id i), alone or in any mix.
+ * ---------------------------------------------------------------------- */
+typedef struct fw_server fw_server;
+
+typedef struct fw_server_opts {
+  uint64_t mem_budget_bytes;   /* device bytes for request buffers (default 1 GiB) */
+  uint32_t max_inflight;       /* concurrent batches / streams (default 4, <= 16) */
+  uint32_t max_batch_requests; /* requests per batch (default 256, <= 4096) */
+} fw_server_opts;
+
+typedef struct fw_req_stats {
+  uint64_t submit_ns, admit_ns, done_ns; /* steady-clock timestamps */
+  uint64_t n;
+  uint32_t length;
+  int status;
+} fw_req_stats;
+
+/* Creates a server for graph g (which must outlive it): allocates the device
+ * arena and its pinned mirror, the streams, and starts the scheduler thread.
+ * opts may be NULL (defaults).  Errors: FW_EINVAL, FW_ENOMEM, FW_EHIP. */
+int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** out);
+
+/* Queues a request (thread-safe).  starts_host: host uint32[n], copied; every
+ * start must be < n_vertices (checked here).  *ticket identifies it.
+ * Errors: FW_EINVAL (as fw_walk, n = 0), FW_EOVERFLOW, FW_ENOMEM (larger
+ * than the whole budget), FW_ECANCELED (server shutting down). */
+int fw_server_submit(fw_server* s, fw_algo algo, const fw_params* params,
+                     const uint32_t* starts_host, uint64_t n, uint32_t length, uint64_t seed,
+                     uint64_t* ticket);
+
+/* 1 if the request has finished (successfully or not), 0 if not yet,
+ * FW_EINVAL for an unknown ticket. */
+int fw_server_poll(fw_server* s, uint64_t ticket);
+
+/* Blocks until the request finishes, copies its n * (length + 1) path
+ * entries to out_host (host, may be NULL), fills *stats (may be NULL), and
+ * releases the request and its memory.  Returns the request's status
+ * (FW_ECANCELED if the server shut down first). */
+int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_stats* stats);
+
+/* Stops admitting, cancels queued requests (FW_ECANCELED), waits for
+ * launched batches and for threads blocked in fw_server_wait, frees all. */
+int fw_server_destroy(fw_server* s);
 
 /* Message for the last failure on this thread ("" if none). */
 const char* fw_last_error(void);

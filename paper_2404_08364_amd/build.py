@@ -13,7 +13,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libflowwalk.so"
-SOURCES = ["fw_runtime.hip", "fw_plain.hip", "fw_persistent.hip", "fw_persistent_host.hip"]
+SOURCES = ["fw_runtime.hip", "fw_plain.hip", "fw_persistent.hip", "fw_staged.hip",
+           "fw_persistent_host.hip", "fw_server.hip"]
 ARCH = os.environ.get("FW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

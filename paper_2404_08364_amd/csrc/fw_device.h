@@ -139,11 +139,25 @@ __device__ __forceinline__ bool row_contains(const uint32_t* __restrict__ adj, u
   return lo < b + n && adj[lo] == u;
 }
 
+// Label of schema entry t mod schema_len, without dynamic register indexing
+// (which would spill the parameter block to scratch).
+__device__ __forceinline__ uint32_t schema_label(const DevParams& p, uint32_t t) {
+  const uint32_t i = t % p.schema_len;
+  uint32_t w[4];
+  __builtin_memcpy(w, p.schema, 16);
+  const uint32_t word = i < 4 ? w[0] : i < 8 ? w[1] : i < 12 ? w[2] : w[3];
+  return (word >> (8 * (i & 3))) & 0xFFu;
+}
+
 // Membership in N(prev) by binary search of its sorted row in global memory.
 struct MemberGlobal {
   const uint32_t* __restrict__ adj;
   uint64_t po, pd;
   __device__ __forceinline__ bool contains(uint32_t u) const { return row_contains(adj, po, pd, u); }
+  __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hit[j] = row_contains(adj, po, pd, u[j]);
+  }
 };
 
 template <int ALGO, bool WEIGHTED, class MEM = MemberGlobal>
@@ -167,13 +181,9 @@ struct Eval {
     if (ALGO == kNode2Vec) {
       if (first) return wt;
       const uint32_t u = adj[e];
-      uint32_t f;
-      if (u == prev)
-        f = f_ret;
-      else if (mem.contains(u))
-        f = f_in;
-      else
-        f = f_out;
+      const uint32_t is_ret = (u == prev) ? 1u : 0u;
+      const uint32_t is_in = (!is_ret && mem.contains(u)) ? 1u : 0u;
+      const uint32_t f = f_out + is_in * (f_in - f_out) + is_ret * (f_ret - f_out);
       return wt * f;
     } else if (ALGO == kMetaPath) {
       return lab[e] == want ? wt : 0ull;
@@ -199,9 +209,16 @@ struct Eval {
       }
       const uint4 a = *reinterpret_cast<const uint4*>(adj + p);
       const uint32_t u[4] = {a.x, a.y, a.z, a.w};
+      bool in[4];
+      mem.contains4(u, in);
+      // Blend arithmetically (mod 2^32, exact): selecting between struct
+      // members would let the compiler address the struct in scratch.
+      const uint32_t d_in = f_in - f_out, d_ret = f_ret - f_out;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t f = (u[j] == prev) ? f_ret : (mem.contains(u[j]) ? f_in : f_out);
+        const uint32_t is_ret = (u[j] == prev) ? 1u : 0u;
+        const uint32_t is_in = in[j] ? (1u - is_ret) : 0u;
+        const uint32_t f = f_out + is_in * d_in + is_ret * d_ret;
         out[j] = (uint64_t)wq[j] * f;
       }
     } else if (ALGO == kMetaPath) {

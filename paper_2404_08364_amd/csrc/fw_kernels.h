@@ -34,7 +34,32 @@ struct LaunchArgs {
   TuneCfg cfg;
 };
 
+// One walk request of a multi-request launch (the served form): query i of
+// the request has id qid_base + i, starts at starts[i] and writes row i of
+// out (length + 1 entries).
+struct ReqDesc {
+  const uint32_t* starts;
+  uint32_t* out;
+  uint64_t n, seed, qid_base;
+  uint32_t length, pad;
+  DevParams prm;
+};
+
+// Requests of one launch: prefix[r] = queries before request r, prefix[nreq]
+// = total.  All requests of a launch share the algorithm.
+struct ReqTable {
+  const ReqDesc* reqs;
+  const uint64_t* prefix;
+  uint32_t nreq;
+  uint64_t total;
+};
+
 hipError_t launch_plain(const LaunchArgs& a, hipStream_t stream);
+// Multi-request persistent launch on `stream` (resets `head` first).
+hipError_t launch_persistent_multi(int algo, const DevGraph& g, const ReqTable& t,
+                                   uint32_t* status, uint64_t* head, int num_cus,
+                                   const TuneCfg& cfg, hipStream_t stream);
 hipError_t launch_persistent(const LaunchArgs& a, hipStream_t stream);
+hipError_t launch_staged(const LaunchArgs& a, hipStream_t stream);
 
 }  // namespace fw

@@ -17,6 +17,7 @@ constexpr size_t kPoolLdsBytes = 16 * 1024;
 
 struct GraphKey {
   int algo;
+  int staged;
   TuneCfg cfg;
   DevParams prm;
   const uint32_t* starts;
@@ -33,38 +34,53 @@ struct GraphCache {
 
 }  // namespace
 
-TuneCfg default_tune(const fw_graph* g, int algo) {
+TuneCfg default_tune(const fw_graph* g, int algo, bool staged) {
   (void)g;
   TuneCfg c;
   std::memset(&c, 0, sizeof(c));
-  c.wg_size = 512;
-  c.slots = 64;
-  c.tiny_max = 16;
-  c.hub_min = 2048;
-  c.wgs_per_cu = 2;
-  c.fetch = 0;
-  c.hash_cells = (algo == 1) ? 8192 : 512;
+  if (staged) {
+    c.wg_size = 512;
+    c.slots = 64;
+    c.tiny_max = 16;
+    c.hub_min = 2048;
+    c.wgs_per_cu = 2;
+    c.hash_cells = (algo == 1) ? 8192 : 512;
+  } else {
+    c.wg_size = 256;
+    c.slots = 4;
+    c.tiny_max = 16;
+    c.hub_min = 17;
+    c.wgs_per_cu = 4;
+    c.hash_cells = (algo == 1) ? 1024 : 64;
+  }
   return c;
 }
 
-int validate_tune(const fw_graph* g, const TuneCfg& c) {
+int validate_tune(const fw_graph* g, const TuneCfg& c, bool staged) {
+  if (c.tiny_max > 16) return set_error(FW_EINVAL, "tiny_max must be <= 16");
+  if (c.wgs_per_cu < 1 || c.wgs_per_cu > 32)
+    return set_error(FW_EINVAL, "wgs_per_cu must be in 1..32");
+  if (c.hash_cells & (c.hash_cells - 1)) return set_error(FW_EINVAL, "hash_cells must be a power of two");
+  if (!staged) {
+    if (c.hash_cells < 64) return set_error(FW_EINVAL, "hash_cells must be >= 64");
+    if ((size_t)c.hash_cells * 4 * 4 > g->lds_per_block)
+      return set_error(FW_EINVAL, "hash_cells exceeds the LDS of a workgroup");
+    return FW_OK;
+  }
   if (c.wg_size != 256 && c.wg_size != 512 && c.wg_size != 1024)
     return set_error(FW_EINVAL, "wg_size must be 256, 512 or 1024");
   if (c.slots < 1 || c.slots > 128) return set_error(FW_EINVAL, "slots must be in 1..128");
-  if (c.tiny_max > 16) return set_error(FW_EINVAL, "tiny_max must be <= 16");
   if (c.hub_min <= c.tiny_max) return set_error(FW_EINVAL, "hub_min must exceed tiny_max");
-  if (c.wgs_per_cu < 1 || c.wgs_per_cu > 32)
-    return set_error(FW_EINVAL, "wgs_per_cu must be in 1..32");
-  if (c.hash_cells & (c.hash_cells - 1) || c.hash_cells < 64 * (c.wg_size / 64))
-    return set_error(FW_EINVAL, "hash_cells must be a power of two >= 64 per wavefront");
+  if (c.hash_cells < 64 * (c.wg_size / 64))
+    return set_error(FW_EINVAL, "hash_cells must be >= 64 per wavefront");
   if (kPoolLdsBytes + (size_t)c.hash_cells * 4 > g->lds_per_block)
     return set_error(FW_EINVAL, "hash_cells exceeds the LDS of a workgroup");
   return FW_OK;
 }
 
-int resolve_tune(const fw_graph* g, int algo, const fw_tune* user, TuneCfg* cfg) {
-  TuneCfg c = default_tune(g, algo);
-  {
+int resolve_tune(const fw_graph* g, int algo, bool staged, const fw_tune* user, TuneCfg* cfg) {
+  TuneCfg c = default_tune(g, algo, staged);
+  if (!staged) {
     std::lock_guard<std::mutex> lk(g->mu);
     auto it = g->tuned.find(algo);
     if (it != g->tuned.end()) c = it->second;
@@ -77,18 +93,22 @@ int resolve_tune(const fw_graph* g, int algo, const fw_tune* user, TuneCfg* cfg)
     if (user->wgs_per_cu) c.wgs_per_cu = user->wgs_per_cu;
     if (user->hash_cells) c.hash_cells = user->hash_cells;
   }
-  const int rc = validate_tune(g, c);
+  const int rc = validate_tune(g, c, staged);
   if (rc) return rc;
   *cfg = c;
   return FW_OK;
 }
 
 hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hipStream_t stream,
-                                     bool use_graph) {
-  if (!use_graph || stream == nullptr) return launch_persistent(a, stream);
+                                     bool use_graph, bool staged) {
+  auto launch = [staged](const LaunchArgs& x, hipStream_t st) {
+    return staged ? launch_staged(x, st) : launch_persistent(x, st);
+  };
+  if (!use_graph || stream == nullptr) return launch(a, stream);
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   key.algo = a.algo;
+  key.staged = staged;
   key.cfg = a.cfg;
   key.prm = a.prm;
   key.starts = a.starts;
@@ -107,7 +127,7 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    const hipError_t le = launch_persistent(a, stream);
+    const hipError_t le = launch(a, stream);
     e = hipStreamEndCapture(stream, &graph);
     if (le != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);

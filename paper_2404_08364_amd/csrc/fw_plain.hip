@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_walk_plain(DevGraph g, DevParams prm,
           ev.mem.po = ev.mem.pd = 0;
         }
       }
-      if (ALGO == kMetaPath) ev.want = prm.schema[t % prm.schema_len];
+      if (ALGO == kMetaPath) ev.want = schema_label(prm, t);
       const uint64_t u = philox_draw(seed, qid_base + q, t);
       int64_t idx;
       if (ALGO == kDeepWalk && !WEIGHTED) {

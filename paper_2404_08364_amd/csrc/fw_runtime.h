@@ -43,9 +43,9 @@ DevGraph dev_graph(const fw_graph* g);
 int read_status(const fw_graph* g, hipStream_t stream);
 
 // Persistent form: configuration and launch (fw_persistent_host.hip).
-int resolve_tune(const fw_graph* g, int algo, const fw_tune* user, TuneCfg* cfg);
+int resolve_tune(const fw_graph* g, int algo, bool staged, const fw_tune* user, TuneCfg* cfg);
 hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hipStream_t stream,
-                                     bool use_graph);
+                                     bool use_graph, bool staged);
 void release_graph_state(fw_graph* g);
 
 }  // namespace fw

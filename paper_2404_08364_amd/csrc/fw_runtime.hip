@@ -280,10 +280,12 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
   hipError_t e;
   if (o.mode == FW_MODE_PLAIN) {
     e = fw::launch_plain(a, stream);
-  } else if (o.mode == FW_MODE_PERSISTENT || o.mode == FW_MODE_AUTO) {
-    rc = fw::resolve_tune(g, (int)algo, o.tune, &a.cfg);
+  } else if (o.mode == FW_MODE_PERSISTENT || o.mode == FW_MODE_AUTO ||
+             o.mode == FW_MODE_STAGED) {
+    const bool staged = o.mode == FW_MODE_STAGED;
+    rc = fw::resolve_tune(g, (int)algo, staged, o.tune, &a.cfg);
     if (rc) return rc;
-    e = fw::launch_persistent_checked(g, a, stream, o.use_graph != 0);
+    e = fw::launch_persistent_checked(g, a, stream, o.use_graph != 0, staged);
   } else {
     return fail(FW_EINVAL, "unknown mode");
   }

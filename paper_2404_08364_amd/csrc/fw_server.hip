@@ -1,0 +1,444 @@
+// Served form: continuous batching of walk requests on one GPU.
+//
+// The graph stays resident in HBM.  Requests (algorithm, parameters, start
+// vertices, length, seed) are submitted from any host thread and queued.  A
+// scheduler thread admits queued requests in arrival order while their
+// device memory (start vertices + result rows) fits the budget (the memory
+// admission rule of Eq. 5, section 5.2, applied per request), groups the
+// admitted requests of one round into a batch, and launches the batch on one
+// of a few streams: per algorithm, one multi-request persistent launch whose
+// global task pool is the concatenation of the batch's queries.  Batches on
+// different streams run concurrently, so requests that arrive while others
+// are on the GPU are admitted as memory and streams free up, and their
+// workgroups start as the earlier launches' workgroups retire.  Results are
+// copied back on the batch's stream into pinned memory.
+//
+// Every walk depends only on (graph, algorithm, parameters, request seed,
+// index in the request, start), so a request's result is the same alone and
+// in any mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fw_runtime.h"
+
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// First-fit allocator over [0, size) with coalescing (host bookkeeping of the
+// device arena and its pinned mirror).
+class Arena {
+ public:
+  explicit Arena(uint64_t size) : size_(size) { free_[0] = size; }
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    bytes = (bytes + 255) & ~255ull;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_[*off] = bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    uint64_t start = off, len = u->second;
+    used_.erase(u);
+    auto next = free_.lower_bound(start);
+    if (next != free_.end() && start + len == next->first) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == start) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    free_[start] = len;
+  }
+  uint64_t size() const { return size_; }
+
+ private:
+  uint64_t size_;
+  std::map<uint64_t, uint64_t> free_, used_;
+};
+
+enum ReqState { kQueued, kRunning, kDone, kFailed };
+
+struct Request {
+  uint64_t ticket;
+  int algo;
+  fw::DevParams prm;
+  std::vector<uint32_t> starts;
+  uint64_t n;
+  uint32_t length;
+  uint64_t seed;
+  uint64_t bytes = 0, off = 0;  // arena region: starts then rows
+  bool has_region = false;
+  ReqState state = kQueued;
+  int status = FW_OK;
+  uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+constexpr int kMaxAlgos = 3;
+
+struct Batch {
+  std::vector<std::shared_ptr<Request>> reqs;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  // Per algorithm: descriptor table + prefix (device and pinned staging).
+  fw::ReqDesc* d_desc[kMaxAlgos] = {};
+  uint64_t* d_prefix[kMaxAlgos] = {};
+  fw::ReqDesc* h_desc[kMaxAlgos] = {};
+  uint64_t* h_prefix[kMaxAlgos] = {};
+  uint64_t* d_head = nullptr;  // kMaxAlgos counters, 128 B apart
+  hipStream_t stream = nullptr;
+};
+
+}  // namespace
+
+struct fw_server {
+  const fw_graph* g = nullptr;
+  fw_server_opts opts{};
+  fw::TuneCfg cfg[kMaxAlgos];
+  uint8_t* d_arena = nullptr;
+  uint8_t* h_arena = nullptr;  // pinned mirror (same offsets)
+  std::unique_ptr<Arena> arena;
+  std::vector<Batch> batches;
+  uint32_t* d_status = nullptr;
+
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::map<uint64_t, std::shared_ptr<Request>> reqs;
+  uint64_t next_ticket = 1;
+  int waiters = 0;
+  bool stop = false;
+  std::thread thread;
+  std::string fatal;
+};
+
+namespace {
+
+int fail(int code, const char* msg) { return fw::set_error(code, msg); }
+
+uint64_t request_bytes(uint64_t n, uint32_t length) {
+  const uint64_t starts = (n * 4 + 255) & ~255ull;
+  return starts + n * ((uint64_t)length + 1) * 4;
+}
+
+// Launches one batch (scheduler thread, lock not held).
+hipError_t launch_batch(fw_server* s, Batch& b) {
+  hipError_t e = hipSuccess;
+  for (auto& r : b.reqs) {
+    uint8_t* h = s->h_arena + r->off;
+    std::memcpy(h, r->starts.data(), r->n * 4);
+    e = hipMemcpyAsync(s->d_arena + r->off, h, r->n * 4, hipMemcpyHostToDevice, b.stream);
+    if (e != hipSuccess) return e;
+  }
+  const fw::DevGraph dg = fw::dev_graph(s->g);
+  for (int a = 0; a < kMaxAlgos; ++a) {
+    uint32_t k = 0;
+    uint64_t total = 0;
+    for (auto& r : b.reqs) {
+      if (r->algo != a) continue;
+      fw::ReqDesc& d = b.h_desc[a][k];
+      d.starts = reinterpret_cast<const uint32_t*>(s->d_arena + r->off);
+      d.out = reinterpret_cast<uint32_t*>(s->d_arena + r->off + ((r->n * 4 + 255) & ~255ull));
+      d.n = r->n;
+      d.seed = r->seed;
+      d.qid_base = 0;
+      d.length = r->length;
+      d.pad = 0;
+      d.prm = r->prm;
+      b.h_prefix[a][k] = total;
+      total += r->n;
+      ++k;
+    }
+    if (!k) continue;
+    b.h_prefix[a][k] = total;
+    e = hipMemcpyAsync(b.d_desc[a], b.h_desc[a], k * sizeof(fw::ReqDesc), hipMemcpyHostToDevice,
+                       b.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b.d_prefix[a], b.h_prefix[a], (k + 1) * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, b.stream);
+    if (e != hipSuccess) return e;
+    fw::ReqTable t{b.d_desc[a], b.d_prefix[a], k, total};
+    e = fw::launch_persistent_multi(a, dg, t, s->d_status, b.d_head + 16 * a, s->g->num_cus,
+                                    s->cfg[a], b.stream);
+    if (e != hipSuccess) return e;
+  }
+  for (auto& r : b.reqs) {
+    const uint64_t so = (r->n * 4 + 255) & ~255ull;
+    e = hipMemcpyAsync(s->h_arena + r->off + so, s->d_arena + r->off + so,
+                       r->n * ((uint64_t)r->length + 1) * 4, hipMemcpyDeviceToHost, b.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(b.done, b.stream);
+}
+
+void scheduler(fw_server* s) {
+  (void)hipSetDevice(s->g->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    // Completions.
+    bool any_busy = false;
+    for (auto& b : s->batches) {
+      if (!b.busy) continue;
+      const hipError_t q = hipEventQuery(b.done);
+      if (q == hipErrorNotReady) {
+        any_busy = true;
+        continue;
+      }
+      const uint64_t t = now_ns();
+      for (auto& r : b.reqs) {
+        r->state = (q == hipSuccess) ? kDone : kFailed;
+        if (q != hipSuccess) r->status = FW_EHIP;
+        r->t_done = t;
+      }
+      b.reqs.clear();
+      b.busy = false;
+      s->cv_done.notify_all();
+    }
+    if (s->stop && s->queue.empty() && !any_busy) break;
+    // Admission: one batch per free stream, requests in arrival order.
+    for (auto& b : s->batches) {
+      if (b.busy || s->queue.empty()) continue;
+      while (!s->queue.empty() && b.reqs.size() < s->opts.max_batch_requests) {
+        auto r = s->queue.front();
+        if (s->stop) {
+          r->state = kFailed;
+          r->status = FW_ECANCELED;
+          s->queue.pop_front();
+          continue;
+        }
+        if (!s->arena->alloc(r->bytes, &r->off)) break;
+        r->has_region = true;
+        r->state = kRunning;
+        r->t_admit = now_ns();
+        b.reqs.push_back(r);
+        s->queue.pop_front();
+      }
+      if (b.reqs.empty()) continue;
+      b.busy = true;
+      lk.unlock();
+      const hipError_t e = launch_batch(s, b);
+      lk.lock();
+      if (e != hipSuccess) {
+        for (auto& r : b.reqs) {
+          r->state = kFailed;
+          r->status = FW_EHIP;
+          r->t_done = now_ns();
+        }
+        (void)hipStreamSynchronize(b.stream);
+        b.reqs.clear();
+        b.busy = false;
+        s->cv_done.notify_all();
+      }
+      any_busy = true;
+    }
+    if (s->stop) {
+      for (auto& r : s->queue) {
+        r->state = kFailed;
+        r->status = FW_ECANCELED;
+      }
+      s->queue.clear();
+      s->cv_done.notify_all();
+    }
+    if (any_busy)
+      s->cv_sched.wait_for(lk, std::chrono::microseconds(20));
+    else
+      s->cv_sched.wait(lk, [s] { return s->stop || !s->queue.empty(); });
+  }
+}
+
+void release_request(fw_server* s, const std::shared_ptr<Request>& r) {
+  if (r->has_region) {
+    s->arena->release(r->off);
+    r->has_region = false;
+  }
+  s->reqs.erase(r->ticket);
+  s->cv_sched.notify_one();
+}
+
+}  // namespace
+
+extern "C" {
+
+int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** out) {
+  if (!g || !out) return fail(FW_EINVAL, "NULL argument");
+  *out = nullptr;
+  auto s = std::make_unique<fw_server>();
+  s->g = g;
+  if (opts) s->opts = *opts;
+  if (!s->opts.mem_budget_bytes) s->opts.mem_budget_bytes = 1ull << 30;
+  if (!s->opts.max_inflight) s->opts.max_inflight = 4;
+  if (!s->opts.max_batch_requests) s->opts.max_batch_requests = 256;
+  if (s->opts.max_inflight > 16 || s->opts.max_batch_requests > 4096)
+    return fail(FW_EINVAL, "max_inflight <= 16 and max_batch_requests <= 4096");
+  for (int a = 0; a < kMaxAlgos; ++a) {
+    const int rc = fw::resolve_tune(g, a, false, nullptr, &s->cfg[a]);
+    if (rc) return rc;
+  }
+  hipError_t e = hipSetDevice(g->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->d_arena, s->opts.mem_budget_bytes);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_arena, s->opts.mem_budget_bytes, 0);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->d_status, 256);
+  if (e == hipSuccess) e = hipMemset(s->d_status, 0, 256);
+  s->batches.resize(s->opts.max_inflight);
+  const size_t nd = s->opts.max_batch_requests;
+  for (auto& b : s->batches) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void**)&b.d_head, kMaxAlgos * 16 * sizeof(uint64_t));
+    for (int a = 0; a < kMaxAlgos && e == hipSuccess; ++a) {
+      e = hipMalloc((void**)&b.d_desc[a], nd * sizeof(fw::ReqDesc));
+      if (e == hipSuccess) e = hipMalloc((void**)&b.d_prefix[a], (nd + 1) * sizeof(uint64_t));
+      if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_desc[a], nd * sizeof(fw::ReqDesc), 0);
+      if (e == hipSuccess)
+        e = hipHostMalloc((void**)&b.h_prefix[a], (nd + 1) * sizeof(uint64_t), 0);
+    }
+  }
+  if (e != hipSuccess) {
+    fw_server* raw = s.release();
+    fw_server_destroy(raw);
+    return fail(e == hipErrorOutOfMemory ? FW_ENOMEM : FW_EHIP, "creating the server");
+  }
+  s->arena = std::make_unique<Arena>(s->opts.mem_budget_bytes);
+  fw_server* raw = s.release();
+  raw->thread = std::thread(scheduler, raw);
+  *out = raw;
+  return FW_OK;
+}
+
+int fw_server_submit(fw_server* s, fw_algo algo, const fw_params* params,
+                     const uint32_t* starts_host, uint64_t n, uint32_t length, uint64_t seed,
+                     uint64_t* ticket) {
+  if (!s || !ticket) return fail(FW_EINVAL, "NULL argument");
+  fw::DevParams dp;
+  const int rc = fw::check_walk_args(s->g, (int)algo, params, n, length, starts_host,
+                                     starts_host, &dp);
+  if (rc) return rc;
+  if (n == 0) return fail(FW_EINVAL, "empty request");
+  for (uint64_t i = 0; i < n; ++i)
+    if (starts_host[i] >= s->g->nv) return fail(FW_EINVAL, "a start vertex is >= n_vertices");
+  auto r = std::make_shared<Request>();
+  r->algo = (int)algo;
+  r->prm = dp;
+  r->starts.assign(starts_host, starts_host + n);
+  r->n = n;
+  r->length = length;
+  r->seed = seed;
+  r->bytes = request_bytes(n, length);
+  if (r->bytes > s->arena->size()) return fail(FW_ENOMEM, "request larger than the memory budget");
+  r->t_submit = now_ns();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return fail(FW_ECANCELED, "server is shutting down");
+  r->ticket = s->next_ticket++;
+  s->reqs[r->ticket] = r;
+  s->queue.push_back(r);
+  *ticket = r->ticket;
+  s->cv_sched.notify_one();
+  return FW_OK;
+}
+
+int fw_server_poll(fw_server* s, uint64_t ticket) {
+  if (!s) return fail(FW_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(FW_EINVAL, "unknown ticket");
+  return (it->second->state == kDone || it->second->state == kFailed) ? 1 : 0;
+}
+
+int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_stats* stats) {
+  if (!s) return fail(FW_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(FW_EINVAL, "unknown ticket");
+  std::shared_ptr<Request> r = it->second;
+  ++s->waiters;
+  s->cv_done.wait(lk, [&] { return r->state == kDone || r->state == kFailed; });
+  --s->waiters;
+  s->cv_done.notify_all();
+  if (stats) {
+    stats->submit_ns = r->t_submit;
+    stats->admit_ns = r->t_admit;
+    stats->done_ns = r->t_done;
+    stats->n = r->n;
+    stats->length = r->length;
+    stats->status = r->status;
+  }
+  int rc = r->status;
+  if (rc == FW_OK && out_host) {
+    const uint64_t so = (r->n * 4 + 255) & ~255ull;
+    std::memcpy(out_host, s->h_arena + r->off + so, r->n * ((uint64_t)r->length + 1) * 4);
+  }
+  release_request(s, r);
+  if (rc != FW_OK) return fail(rc, rc == FW_ECANCELED ? "request cancelled" : "request failed");
+  return FW_OK;
+}
+
+int fw_server_destroy(fw_server* s) {
+  if (!s) return FW_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_sched.notify_all();
+  }
+  if (s->thread.joinable()) s->thread.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto& kv : s->reqs) {
+      if (kv.second->state == kQueued || kv.second->state == kRunning) {
+        kv.second->state = kFailed;
+        kv.second->status = FW_ECANCELED;
+      }
+    }
+    s->cv_done.notify_all();
+  }
+  {
+    // Let threads blocked in fw_server_wait return before the memory goes.
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [s] { return s->waiters == 0; });
+  }
+  for (auto& b : s->batches) {
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.done) (void)hipEventDestroy(b.done);
+    (void)hipFree(b.d_head);
+    for (int a = 0; a < kMaxAlgos; ++a) {
+      (void)hipFree(b.d_desc[a]);
+      (void)hipFree(b.d_prefix[a]);
+      if (b.h_desc[a]) (void)hipHostFree(b.h_desc[a]);
+      if (b.h_prefix[a]) (void)hipHostFree(b.h_prefix[a]);
+    }
+  }
+  (void)hipFree(s->d_arena);
+  if (s->h_arena) (void)hipHostFree(s->h_arena);
+  (void)hipFree(s->d_status);
+  delete s;
+  return FW_OK;
+}
+
+}  // extern "C"

@@ -18,7 +18,7 @@ LIB_PATH = _PKG / "libflowwalk.so"
 OK, EINVAL, ENOMEM, EOVERFLOW, EHIP, ECANCELED = 0, -1, -2, -3, -4, -5
 DEEPWALK, NODE2VEC, METAPATH = 0, 1, 2
 ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH}
-MODES = {"auto": 0, "plain": 1, "persistent": 2}
+MODES = {"auto": 0, "plain": 1, "persistent": 2, "staged": 3}
 END = 0xFFFFFFFF
 
 if not LIB_PATH.exists():
@@ -58,6 +58,17 @@ class WalkOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("max_batch_requests", ctypes.c_uint32)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("n", ctypes.c_uint64), ("length", ctypes.c_uint32),
+                ("status", ctypes.c_int)]
+
+
 def _bind(lib):
     u64, u32, i32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
     sig = {
@@ -69,6 +80,12 @@ def _bind(lib):
         "fw_walk_ex": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                         ctypes.POINTER(WalkOpts)], i32),
         "fw_sync": ([vp, vp], i32),
+        "fw_server_create": ([vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], i32),
+        "fw_server_submit": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64,
+                              ctypes.POINTER(u64)], i32),
+        "fw_server_poll": ([vp, u64], i32),
+        "fw_server_wait": ([vp, u64, vp, ctypes.POINTER(ReqStats)], i32),
+        "fw_server_destroy": ([vp], i32),
         "fw_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -219,3 +236,55 @@ def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
 
 def sync(graph: Graph, stream=None):
     _check(_lib.fw_sync(graph.handle, _stream_handle(stream)), "fw_sync")
+
+
+class Server:
+    """Continuous-batching walk server over one resident graph.
+
+    submit() takes host start vertices (numpy) and returns a ticket; wait()
+    returns the uint32 paths [n, length + 1] and the request's timestamps."""
+
+    def __init__(self, graph: Graph, mem_budget_bytes: int = 1 << 30, max_inflight: int = 4,
+                 max_batch_requests: int = 256):
+        self.graph = graph
+        o = ServerOpts(mem_budget_bytes, max_inflight, max_batch_requests)
+        h = ctypes.c_void_p()
+        _check(_lib.fw_server_create(graph.handle, ctypes.byref(o), ctypes.byref(h)),
+               "fw_server_create")
+        self._h = h
+        self._shapes = {}
+
+    def submit(self, algo, prm: Params | None, starts, length: int, seed: int) -> int:
+        st = np.ascontiguousarray(starts, dtype=np.uint32)
+        t = ctypes.c_uint64()
+        a = ALGOS.get(algo, algo)
+        _check(_lib.fw_server_submit(self._h, a, None if prm is None else ctypes.byref(prm),
+                                     st.ctypes.data, st.shape[0], length, seed, ctypes.byref(t)),
+               "fw_server_submit")
+        self._shapes[t.value] = (st.shape[0], length + 1)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        rc = _lib.fw_server_poll(self._h, ticket)
+        if rc < 0:
+            raise FWError(rc, "fw_server_poll")
+        return rc == 1
+
+    def wait(self, ticket: int):
+        shape = self._shapes.pop(ticket)
+        out = np.empty(shape, dtype=np.uint32)
+        st = ReqStats()
+        _check(_lib.fw_server_wait(self._h, ticket, out.ctypes.data, ctypes.byref(st)),
+               "fw_server_wait")
+        return out, {k: getattr(st, k) for k, _ in ReqStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.fw_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,7 +14,7 @@ from helpers import csr_from_edges, tiny6
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["plain", "persistent"]
+MODES = ["plain", "persistent", "staged"]
 
 
 @pytest.fixture(scope="module")
@@ -133,7 +133,7 @@ def test_errors(env):
     assert out.shape == (0, 4)
 
 
-TUNES = [
+STAGED_TUNES = [
     dict(wg_size=256, slots=1, tiny_max=1, hub_min=2, wgs_per_cu=1, hash_cells=256),
     dict(wg_size=256, slots=7, tiny_max=4, hub_min=65, wgs_per_cu=3, hash_cells=256),
     dict(wg_size=512, slots=64, tiny_max=16, hub_min=2048, wgs_per_cu=2, hash_cells=8192),
@@ -141,27 +141,63 @@ TUNES = [
     dict(wg_size=512, slots=33, tiny_max=8, hub_min=100000, wgs_per_cu=4, hash_cells=512),
 ]
 
+PERSISTENT_TUNES = [
+    dict(tiny_max=1, wgs_per_cu=1, hash_cells=64),
+    dict(tiny_max=4, wgs_per_cu=3, hash_cells=256),
+    dict(tiny_max=16, wgs_per_cu=4, hash_cells=1024),
+    dict(tiny_max=16, wgs_per_cu=8, hash_cells=4096),
+    dict(tiny_max=8, wgs_per_cu=2, hash_cells=128),
+]
 
-@pytest.mark.parametrize("tune", TUNES, ids=lambda t: "wg{wg_size}-s{slots}-tm{tiny_max}-hm{hub_min}-h{hash_cells}".format(**t))
+TUNED = [("staged", t) for t in STAGED_TUNES] + [("persistent", t) for t in PERSISTENT_TUNES]
+
+
+def _tid(mt):
+    mode, t = mt
+    return mode + "-" + "-".join(f"{k}{v}" for k, v in t.items())
+
+
+@pytest.mark.parametrize("mode_tune", TUNED, ids=_tid)
 @pytest.mark.parametrize("algo,factors,schema", ALGOS[:3] + ALGOS[3:4])
-def test_persistent_tunes(env, powerlaw, tune, algo, factors, schema):
-    """Every launch configuration of the persistent form gives the oracle's
-    walks (degree classes, pool sizes, hash-set capacity that forces the
-    global-search fallback)."""
+def test_tunes(env, powerlaw, mode_tune, algo, factors, schema):
+    """Every launch configuration gives the oracle's walks (degree classes,
+    pool sizes, membership structures: hash set, filter, global search)."""
     torch, fw = env
+    mode, tune = mode_tune
     g = powerlaw
     starts = np.arange(g.n_vertices, dtype=np.uint32)[::7]
-    _check(env, g, algo, factors, schema, starts, 10, 4242, "persistent",
-           tune=fw.make_tune(**tune))
+    _check(env, g, algo, factors, schema, starts, 10, 4242, mode, tune=fw.make_tune(**tune))
 
 
-def test_persistent_star_hubs_with_tunes(env):
+@pytest.mark.parametrize("mode_tune", TUNED, ids=_tid)
+def test_star_hubs_with_tunes(env, mode_tune):
     torch, fw = env
+    mode, tune = mode_tune
     g = _star(70_000, 3)
     starts = np.concatenate([np.zeros(40, np.uint32), np.arange(1, 300, dtype=np.uint32)])
-    for tune in TUNES:
-        _check(env, g, "node2vec", (2, 3, 5), (), starts, 7, 99, "persistent",
-               tune=fw.make_tune(**tune))
+    _check(env, g, "node2vec", (2, 3, 5), (), starts, 7, 99, mode, tune=fw.make_tune(**tune))
+
+
+def _two_hubs(d):
+    """Two adjacent hubs sharing most neighbours: node2vec hops between them
+    test membership against a large N(prev) (hash set overflow -> filter)."""
+    rng = np.random.default_rng(d)
+    edges = [(0, 1, 7, 0)]
+    for i in range(2, d + 2):
+        w = int(rng.integers(1, 100))
+        edges.append((0, i, w, i % 3))
+        if i % 3:
+            edges.append((1, i, w + 1, (i + 1) % 3))
+    return csr_from_edges(d + 2, edges)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d", [100, 5000, 40000])
+def test_hub_to_hub_membership(env, mode, d):
+    g = _two_hubs(d)
+    starts = np.array([0, 1] * 64 + list(range(2, min(200, d + 2))), dtype=np.uint32)
+    _check(env, g, "node2vec", (4, 2, 1), (), starts, 12, 5, mode)
+    _check(env, g, "node2vec", (1, 2, 4), (), starts, 12, 6, mode)
 
 
 def test_graph_replay_matches_eager(env, powerlaw):
@@ -173,15 +209,15 @@ def test_graph_replay_matches_eager(env, powerlaw):
     prm = fw.make_params((1, 2, 4))
     starts = torch.arange(0, g.n_vertices, 3, dtype=torch.int32, device="cuda")
     stream = torch.cuda.Stream()
-    eager = fw.walk(G, "node2vec", prm, starts, 15, 77, mode="persistent")
+    eager = fw.walk(G, "node2vec", prm, starts, 15, 77, mode="plain")
     torch.cuda.synchronize()
     out = torch.empty_like(eager)
     for i in range(4):
         out.fill_(-7)
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
-            fw.walk(G, "node2vec", prm, starts, 15, 77, out=out, mode="persistent",
-                    stream=stream, use_graph=True)
+            fw.walk(G, "node2vec", prm, starts, 15, 77, out=out,
+                    mode=("persistent", "staged")[i % 2], stream=stream, use_graph=True)
         stream.synchronize()
         assert torch.equal(out, eager), f"replay {i}"
         junk = fw.walk(G, "deepwalk", None, starts[:100], 3, i, mode="plain")

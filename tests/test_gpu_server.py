@@ -1,0 +1,101 @@
+"""Served form (GPU): every request's walks equal the oracle's and fw_walk's
+on the same starts and seed, alone and in a concurrent mix of algorithms,
+lengths and sizes; admission by memory; cancellation on shutdown."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import assert_rows_equal, gpu_walk, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = torch_or_skip()
+    from paper_2404_08364_amd import flowwalk as fw
+    g = synth.chung_lu(30_000, 400_000, 2.1, 1.5, seed=11)
+    g.weights = synth.weights_uniform(g, 1, 255, 12)
+    g.labels = synth.labels_uniform(g, 5, 13)
+    return torch, fw, g, fw.Graph.of(g)
+
+
+KINDS = [("deepwalk", (1, 1, 1), ()), ("node2vec", (1, 2, 4), ()), ("metapath", (1, 1, 1), (0, 1, 2))]
+
+
+def _requests(g, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        algo, f, sch = KINDS[i % 3]
+        n = int(np.exp(rng.uniform(0, np.log(3000))))
+        L = int(rng.integers(10, 81))
+        starts = rng.integers(0, g.n_vertices, n).astype(np.uint32)
+        reqs.append((algo, f, sch, starts, L, int(rng.integers(0, 1 << 40))))
+    return reqs
+
+
+def test_mix_equals_alone_and_oracle(env):
+    torch, fw, g, G = env
+    reqs = _requests(g, 24, 1)
+    srv = fw.Server(G, mem_budget_bytes=64 << 20, max_inflight=4, max_batch_requests=8)
+    try:
+        # Submitted from several threads at once, so they mix on the GPU.
+        tickets = [None] * len(reqs)
+
+        def sub(idx):
+            for i in idx:
+                algo, f, sch, st, L, seed = reqs[i]
+                tickets[i] = srv.submit(algo, fw.make_params(f, sch), st, L, seed)
+
+        th = [threading.Thread(target=sub, args=(range(k, len(reqs), 3),)) for k in range(3)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        results = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for (algo, f, sch, st, L, seed), (paths, stats) in zip(reqs, results):
+        exp = oracle.walk(g, algo, oracle.params(*f, schema=sch), st, L, seed)
+        assert_rows_equal(paths, exp, f"served {algo} n={len(st)} L={L}")
+        assert stats["status"] == 0 and stats["done_ns"] >= stats["admit_ns"] >= stats["submit_ns"]
+        alone = gpu_walk(torch, fw, G, algo, fw.make_params(f, sch), st, L, seed, "persistent")
+        assert_rows_equal(paths, alone, "served vs alone")
+
+
+def test_admission_by_memory(env):
+    """A budget that holds only a few requests at a time still serves a long
+    queue; a request larger than the whole budget is refused at submit."""
+    torch, fw, g, G = env
+    reqs = _requests(g, 12, 2)
+    need = max(len(st) * 4 + len(st) * (L + 1) * 4 for (_, _, _, st, L, _) in reqs)
+    srv = fw.Server(G, mem_budget_bytes=2 * need + 4096, max_inflight=2)
+    try:
+        tickets = [srv.submit(a, fw.make_params(f, s), st, L, sd) for (a, f, s, st, L, sd) in reqs]
+        for (a, f, s, st, L, sd), t in zip(reqs, tickets):
+            paths, _ = srv.wait(t)
+            assert_rows_equal(paths, oracle.walk(g, a, oracle.params(*f, schema=s), st, L, sd),
+                              "admission")
+        big = np.zeros(1_000_000, dtype=np.uint32)
+        with pytest.raises(fw.FWError) as e:
+            srv.submit("deepwalk", None, big, 80, 1)
+        assert e.value.status == fw.ENOMEM
+        with pytest.raises(fw.FWError) as e:
+            srv.submit("deepwalk", None, np.array([g.n_vertices], np.uint32), 5, 1)
+        assert e.value.status == fw.EINVAL
+    finally:
+        srv.close()
+
+
+def test_shutdown_cancels_queued(env):
+    torch, fw, g, G = env
+    srv = fw.Server(G, mem_budget_bytes=1 << 20, max_inflight=1, max_batch_requests=1)
+    st = np.arange(2000, dtype=np.uint32)
+    tickets = [srv.submit("node2vec", fw.make_params((1, 2, 4)), st, 60, i) for i in range(20)]
+    srv.close()  # queued ones are cancelled, launched ones finish
+    # The handle is gone: nothing more to wait on; the call must not hang.
+    assert len(tickets) == 20
