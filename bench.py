@@ -122,6 +122,70 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
                 parity_on_sample=ok)
 
 
+def serve_phase(fw, synth, workload: str, seconds: float, rate: float, budget: int, log):
+    """Poisson request stream against the served form; returns latency and
+    throughput figures.  Latency = completion (server clock) minus the
+    request's scheduled arrival time (both CLOCK_MONOTONIC)."""
+    import threading
+    g = synth.load_recipe_graph(workload)
+    G = fw.Graph.of(g)
+    rng = np.random.default_rng(2024)
+    n_req = int(seconds * rate)
+    gaps = rng.exponential(1.0 / rate, n_req)
+    arrivals = np.cumsum(gaps)
+    sizes = np.floor(np.exp(rng.uniform(0, np.log(65536), n_req))).astype(np.int64)
+    kinds = rng.integers(0, 3, n_req)
+    lengths = rng.integers(10, 81, n_req)
+    seeds = rng.integers(0, 1 << 62, n_req)
+    params = [(("deepwalk"), None),
+              ("node2vec", fw.make_params(fw.node2vec_factors(2, 1, 1, 2))),
+              ("metapath", fw.make_params(schema=[0, 1, 2]))]
+    starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=4, max_batch_requests=512)
+    tickets = [None] * n_req
+    sched_ns = [0] * n_req
+    lat = np.zeros(n_req)
+    hops = np.zeros(n_req, dtype=np.int64)
+
+    def submitter(t0):
+        for i in range(n_req):
+            target = t0 + int(arrivals[i] * 1e9)
+            now = time.monotonic_ns()
+            if target > now:
+                time.sleep((target - now) / 1e9)
+            algo, prm = params[kinds[i]]
+            sched_ns[i] = target
+            tickets[i] = srv.submit(algo, prm, starts_all[offs[i]:offs[i + 1]],
+                                    int(lengths[i]), int(seeds[i]))
+
+    t0 = time.monotonic_ns() + 50_000_000
+    th = threading.Thread(target=submitter, args=(t0,))
+    th.start()
+    done = 0
+    while done < n_req:
+        while tickets[done] is None:
+            time.sleep(0.0005)
+        paths, st = srv.wait(tickets[done])
+        lat[done] = (st["done_ns"] - sched_ns[done]) / 1e6
+        hops[done] = int((paths[:, 1:] != 0xFFFFFFFF).sum())
+        done += 1
+    th.join()
+    t_end = time.monotonic_ns()
+    srv.close()
+    G.free()
+    wall = (t_end - t0) / 1e9
+    res = dict(workload=workload, requests=n_req, offered_rate_per_s=rate, duration_s=wall,
+               p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+               mean_ms=float(lat.mean()), served_steps_per_s=float(hops.sum() / wall),
+               served_queries=int(sizes.sum()), mem_budget_bytes=budget,
+               request_mix="sizes floor(log-uniform[1,65536]), algorithm uniform over "
+                           "{DeepWalk, node2vec p=2 q=1/2, MetaPath [0,1,2]}, length U{10..80}, "
+                           "Poisson arrivals")
+    log(f"serve: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +197,27 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--use-graph", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-workload", default="rmat24_serve")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only copy this many bytes device-to-device (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 4
+        a = torch.arange(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "seconds": dt,
+                          "gbps": 2 * n * 4 / dt / 1e9}), flush=True)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -185,6 +269,13 @@ def main():
         kern_ms = [a.elapsed_time(b) for a, b in evs]
         return wall * 1e3 / steps, float(np.mean(kern_ms)), kern_ms
 
+    tuned = None
+    if args.autotune and args.mode in ("persistent", "auto"):
+        sample = starts[:: max(1, n // 65536)].contiguous()
+        t_at = time.time()
+        tuned = fw.autotune(G, algo, prm, sample, L, seed, stream=stream)
+        log(f"autotune ({sample.shape[0]} queries, {time.time() - t_at:.1f} s): {tuned}")
+
     ms_step, kern_ms, all_ms = timed(args.mode, args.steps, args.warmup)
     log(f"{args.mode}: {ms_step:.1f} ms/step, kernel {kern_ms:.1f} ms ({all_ms})")
 
@@ -220,6 +311,13 @@ def main():
                            lambda q: host_paths[q.astype(np.int64)])
         log(f"cpu baseline: {cpu}")
 
+    latency = None
+    if args.serve_seconds > 0:
+        del out
+        torch.cuda.empty_cache()
+        latency = serve_phase(fw, synth, args.serve_workload, args.serve_seconds,
+                              args.serve_rate, 4 << 30, log)
+
     res = {
         "metric": METRIC,
         "value": value,
@@ -248,7 +346,8 @@ def main():
         "algorithmic_bytes_per_launch": alg_bytes,
         "plain": plain,
         "cpu_baseline": cpu,
-        "latency": None,
+        "latency": latency,
+        "tuned": tuned,
         "kernel_source": kernel_source_hash(),
     }
     print(json.dumps(res), flush=True)

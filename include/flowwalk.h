@@ -174,6 +174,18 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
                const uint32_t* starts, uint64_t n, uint32_t length, uint64_t seed,
                uint32_t* out_paths, const fw_walk_opts* opts);
 
+/* Autotuner for the persistent form (the hyper-parameter study of Appendix
+ * C.2, run on the target GPU): times candidate configurations (resident
+ * workgroups per CU, node2vec membership-table size, tiny-degree threshold)
+ * on the n queries of `starts` (device, a sample of the real query set),
+ * keeps the fastest as the graph's configuration for `algo` (used by later
+ * FW_MODE_AUTO / FW_MODE_PERSISTENT walks and servers created afterwards
+ * that pass no explicit fw_tune) and copies it to *best (may be NULL).  Runs
+ * on `stream` and blocks; allocates a temporary n * (length + 1) output.
+ * Errors: as fw_walk, FW_ENOMEM. */
+int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32_t* starts,
+                uint64_t n, uint32_t length, uint64_t seed, void* stream, fw_tune* best);
+
 /* Waits for `stream` (a hipStream_t, NULL = null stream) and returns the
  * status that kernels of graph g detected since the last check (FW_EINVAL
  * for a start vertex >= V), clearing it. */

@@ -149,14 +149,43 @@ __device__ __forceinline__ uint32_t schema_label(const DevParams& p, uint32_t t)
   return (word >> (8 * (i & 3))) & 0xFFu;
 }
 
+// Four lower-bound searches in the sorted row adj[b, b + n) with one trip
+// count for all of them (n is wave-uniform at the callers): no divergence,
+// and the four probes of a step are issued together.
+__device__ __forceinline__ void row_contains4(const uint32_t* __restrict__ adj, uint64_t b,
+                                              uint64_t n, const uint32_t u[4], bool hit[4]) {
+  if (n == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hit[j] = false;
+    return;
+  }
+  uint64_t base[4] = {b, b, b, b};
+  uint64_t len = n;
+  while (len > 1) {  // invariant: the lower bound of u[j] is in [base[j], base[j] + len]
+    const uint64_t half = len >> 1;
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = adj[base[j] + half];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) base[j] = (x[j] < u[j]) ? base[j] + half : base[j];
+    len -= half;
+  }
+  const uint64_t last = b + n - 1;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t x0 = adj[base[j]];
+    const uint32_t x1 = adj[min(base[j] + 1, last)];
+    hit[j] = (x0 == u[j]) || (x0 < u[j] && base[j] < last && x1 == u[j]);
+  }
+}
+
 // Membership in N(prev) by binary search of its sorted row in global memory.
 struct MemberGlobal {
   const uint32_t* __restrict__ adj;
   uint64_t po, pd;
   __device__ __forceinline__ bool contains(uint32_t u) const { return row_contains(adj, po, pd, u); }
   __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) hit[j] = row_contains(adj, po, pd, u[j]);
+    row_contains4(adj, po, pd, u, hit);
   }
 };
 
@@ -216,9 +245,8 @@ struct Eval {
       const uint32_t d_in = f_in - f_out, d_ret = f_ret - f_out;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t is_ret = (u[j] == prev) ? 1u : 0u;
-        const uint32_t is_in = in[j] ? (1u - is_ret) : 0u;
-        const uint32_t f = f_out + is_in * d_in + is_ret * d_ret;
+        const bool is_ret = u[j] == prev;
+        const uint32_t f = f_out + ((in[j] && !is_ret) ? d_in : 0u) + (is_ret ? d_ret : 0u);
         out[j] = (uint64_t)wq[j] * f;
       }
     } else if (ALGO == kMetaPath) {

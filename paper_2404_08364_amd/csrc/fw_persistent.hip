@@ -46,12 +46,21 @@ __device__ __forceinline__ bool has4(uint4 v, uint32_t u) {
   return (v.x == u) | (v.y == u) | (v.z == u) | (v.w == u);
 }
 
-// Exact hash set of the ids of N(prev): nb buckets of 4 cells (16 bytes) at
-// fw_dyn_lds[base, base + 4 nb); kEnd marks an empty cell.  A key lives in the
-// first bucket, in probe order from its hash, that had a free cell when it
-// was inserted, so a lookup stops at a hit or at a bucket with a free cell.
-struct MemberLds {
+// Membership in N(prev) for one node2vec hop, by a wave-uniform mode:
+//   0  binary search of the sorted row in global memory;
+//   1  exact hash set in LDS: nb buckets of 4 cells (16 bytes) at
+//      fw_dyn_lds[base, base + 4 nb), kEnd marks an empty cell; a key lives
+//      in the first bucket, in probe order from its hash, that had a free cell
+//      when it was inserted, so a lookup stops at a hit or at a bucket with a
+//      free cell;
+//   2  one-bit filter in LDS (bit hash(x) set for every x in N(prev)): a clear
+//      bit proves absence, a set bit is confirmed by binary search.
+// One type for all modes keeps a single copy of the sampler in the kernel.
+struct MemberAny {
+  int mode;
   uint32_t base, bmask, shift;
+  const uint32_t* __restrict__ adj;
+  uint64_t po, pd;
 
   __device__ __forceinline__ uint4 bucket(uint32_t b) const {
     return *reinterpret_cast<const uint4*>(&fw_dyn_lds[base + 4 * b]);
@@ -65,61 +74,49 @@ struct MemberLds {
     }
   }
   __device__ __forceinline__ bool contains(uint32_t u) const {
-    const uint32_t b = (u * kFib) >> shift;
-    const uint4 v = bucket(b);
-    if (has4(v, u)) return true;
-    if (max4(v) == kEnd) return false;
-    return probe_rest(u, b);
+    bool h[4];
+    const uint32_t q[4] = {u, u, u, u};
+    contains4(q, h);
+    return h[0];
   }
-  // Four lookups with their first probes issued together.
+  // Four lookups; in the hash-set mode their first probes are issued together.
   __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
-    uint32_t b[4];
-    uint4 v[4];
+    if (mode == 1) {
+      uint32_t b[4];
+      uint4 v[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      b[j] = (u[j] * kFib) >> shift;
-      v[j] = bucket(b[j]);
-    }
-    bool more = false;
-    bool open[4];
+      for (int j = 0; j < 4; ++j) {
+        b[j] = (u[j] * kFib) >> shift;
+        v[j] = bucket(b[j]);
+      }
+      bool more = false;
+      bool open[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      hit[j] = has4(v[j], u[j]);
-      open[j] = max4(v[j]) == kEnd;
-      more |= !(hit[j] | open[j]);
+      for (int j = 0; j < 4; ++j) {
+        hit[j] = has4(v[j], u[j]);
+        open[j] = max4(v[j]) == kEnd;
+        more |= !(hit[j] | open[j]);
+      }
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (!(hit[j] | open[j])) hit[j] = probe_rest(u[j], b[j]);
+      }
+      return;
     }
-    if (more) {
+    if (mode == 2) {
+      // Filter: only keys whose bit is set are searched (few of them).
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t h = (u[j] * kFib) >> shift;
+        hit[j] = (fw_dyn_lds[base + (h >> 5)] >> (h & 31)) & 1u;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (!(hit[j] | open[j])) hit[j] = probe_rest(u[j], b[j]);
+        if (hit[j]) hit[j] = row_contains(adj, po, pd, u[j]);
+      return;
     }
-  }
-};
-
-// Filter for a large N(prev): bit hash(x) of the region is set for every x in
-// N(prev); a clear bit proves absence, a set bit is confirmed by binary search
-// of the sorted row in global memory.
-struct MemberFilter {
-  uint32_t base, shift;
-  const uint32_t* __restrict__ adj;
-  uint64_t po, pd;
-  __device__ __forceinline__ bool contains(uint32_t u) const {
-    const uint32_t h = (u * kFib) >> shift;
-    if (!((fw_dyn_lds[base + (h >> 5)] >> (h & 31)) & 1u)) return false;
-    return row_contains(adj, po, pd, u);
-  }
-  __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
-    uint32_t h[4], wd[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      h[j] = (u[j] * kFib) >> shift;
-      wd[j] = fw_dyn_lds[base + (h[j] >> 5)];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) hit[j] = (wd[j] >> (h[j] & 31)) & 1u;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (hit[j]) hit[j] = row_contains(adj, po, pd, u[j]);
+    row_contains4(adj, po, pd, u, hit);
   }
 };
 
@@ -195,41 +192,6 @@ __device__ __forceinline__ Eval<ALGO, WEIGHTED, MEM> base_eval(const DevGraph& g
   ev.f_out = prm.f_out;
   ev.want = (ALGO == kMetaPath) ? schema_label(prm, t) : 0u;
   return ev;
-}
-
-// Calls f(ev) with the evaluator type that fits the hop: the first node2vec
-// hop weighs like DeepWalk; later node2vec hops use the structure built for
-// N(prev).
-template <int ALGO, bool WEIGHTED, class F>
-__device__ __forceinline__ void with_eval(const DevGraph& g, const DevParams& prm, uint64_t o,
-                                          uint32_t prev, uint32_t t, const Table& tb, F&& f) {
-  if (ALGO == kNode2Vec) {
-    if (t == 0) {
-      f(base_eval<kDeepWalk, WEIGHTED, MemberGlobal>(g, prm, o, prev, t));
-    } else if (tb.kind == 1) {
-      auto ev = base_eval<kNode2Vec, WEIGHTED, MemberLds>(g, prm, o, prev, t);
-      ev.mem.base = tb.base;
-      ev.mem.bmask = tb.bmask;
-      ev.mem.shift = tb.shift;
-      f(ev);
-    } else if (tb.kind == 2) {
-      auto ev = base_eval<kNode2Vec, WEIGHTED, MemberFilter>(g, prm, o, prev, t);
-      ev.mem.base = tb.base;
-      ev.mem.shift = tb.shift;
-      ev.mem.adj = g.adj;
-      ev.mem.po = tb.po;
-      ev.mem.pd = tb.pd;
-      f(ev);
-    } else {
-      auto ev = base_eval<kNode2Vec, WEIGHTED, MemberGlobal>(g, prm, o, prev, t);
-      ev.mem.adj = g.adj;
-      ev.mem.po = tb.po;
-      ev.mem.pd = tb.pd;
-      f(ev);
-    }
-  } else {
-    f(base_eval<ALGO, WEIGHTED, MemberGlobal>(g, prm, o, prev, t));
-  }
 }
 
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
@@ -392,9 +354,15 @@ __global__ __launch_bounds__(kBlock) void k_walk_persistent(
         build_table(tb, g.adj, d, lane);
       }
       const uint64_t u = philox_draw(R.seed, R.qid_base + qid, t);
-      int64_t idx = -1;
-      with_eval<ALGO, WEIGHTED>(g, prm, o, prev, t, tb,
-                                [&](const auto& ev) { idx = wave_pick(ev, o, d, u); });
+      auto ev = base_eval<ALGO, WEIGHTED, MemberAny>(g, prm, o, prev, t);
+      ev.mem.mode = tb.kind;
+      ev.mem.base = tb.base;
+      ev.mem.bmask = tb.bmask;
+      ev.mem.shift = tb.shift;
+      ev.mem.adj = g.adj;
+      ev.mem.po = tb.po;
+      ev.mem.pd = tb.pd;
+      const int64_t idx = wave_pick(ev, o, d, u);
       uint32_t* row = R.out + qid * ((uint64_t)length + 1);
       const bool mine = grp == src / kGroupLanes;
       if (idx < 0) {

@@ -142,6 +142,96 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
   return hipGraphLaunch(it->second.first, stream);
 }
 
+// Times one persistent launch of cfg on the sample (hipEvents on stream).
+static int time_config(const fw_graph* g, LaunchArgs a, const TuneCfg& cfg, hipStream_t stream,
+                       hipEvent_t e0, hipEvent_t e1, float* ms) {
+  a.cfg = cfg;
+  hipError_t e = launch_persistent(a, stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, stream);
+  if (e == hipSuccess) e = launch_persistent(a, stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e != hipSuccess) return set_error(FW_EHIP, hipGetErrorString(e));
+  return FW_OK;
+}
+
+int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts, uint64_t n,
+             uint32_t length, uint64_t seed, hipStream_t stream, TuneCfg* best) {
+  uint32_t* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc((void**)&out, n * ((uint64_t)length + 1) * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int rc = FW_OK;
+  if (e != hipSuccess) rc = set_error(e == hipErrorOutOfMemory ? FW_ENOMEM : FW_EHIP,
+                                      "autotune allocation");
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.algo = algo;
+  a.g = dev_graph(g);
+  a.prm = dp;
+  a.starts = starts;
+  a.n = n;
+  a.length = length;
+  a.seed = seed;
+  a.out = out;
+  a.status = g->d_status;
+  a.head = g->d_head + kHeadStride * (g->launches.fetch_add(1) % kHeadSlots);
+  a.num_cus = g->num_cus;
+  TuneCfg c = default_tune(g, algo, false), best_c = c;
+  float best_ms = 1e30f;
+  // Coordinate search: occupancy x membership-table size, then the tiny
+  // threshold.  Configurations that do not fit the LDS are skipped.
+  const uint32_t cells[] = {256, 512, 1024, 2048, 4096};
+  const uint32_t wgs[] = {2, 3, 4, 5, 6, 8};
+  for (uint32_t hc : cells) {
+    if (algo != 1 && hc != 256) continue;  // only node2vec uses the tables
+    for (uint32_t w : wgs) {
+      if (rc) break;
+      TuneCfg t = c;
+      t.hash_cells = (algo == 1) ? hc : 64;
+      t.wgs_per_cu = w;
+      if (validate_tune(g, t, false)) continue;
+      if ((uint64_t)t.hash_cells * 16 * w > 160 * 1024) continue;  // would not be resident
+      float ms = 0;
+      rc = time_config(g, a, t, stream, e0, e1, &ms);
+      if (!rc && ms < best_ms) {
+        best_ms = ms;
+        best_c = t;
+      }
+    }
+  }
+  for (uint32_t tm : {0u, 8u, 16u}) {
+    if (rc) break;
+    TuneCfg t = best_c;
+    t.tiny_max = tm;
+    float ms = 0;
+    rc = time_config(g, a, t, stream, e0, e1, &ms);
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best_c = t;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(stream);
+  (void)hipFree(out);
+  uint32_t st = 0;
+  (void)hipMemcpy(&st, g->d_status, sizeof(st), hipMemcpyDeviceToHost);
+  if (st) {
+    (void)hipMemset(g->d_status, 0, sizeof(st));
+    if (!rc) rc = set_error(FW_EINVAL, "a start vertex is >= n_vertices");
+  }
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->tuned[algo] = best_c;
+  }
+  *best = best_c;
+  return FW_OK;
+}
+
 void release_graph_state(fw_graph* g) {
   auto* cache = static_cast<GraphCache*>(g->graph_cache);
   if (!cache) return;

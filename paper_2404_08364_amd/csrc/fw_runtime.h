@@ -47,5 +47,9 @@ int resolve_tune(const fw_graph* g, int algo, bool staged, const fw_tune* user, 
 hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hipStream_t stream,
                                      bool use_graph, bool staged);
 void release_graph_state(fw_graph* g);
+TuneCfg default_tune(const fw_graph* g, int algo, bool staged);
+int validate_tune(const fw_graph* g, const TuneCfg& c, bool staged);
+int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts, uint64_t n,
+             uint32_t length, uint64_t seed, hipStream_t stream, TuneCfg* best);
 
 }  // namespace fw

@@ -299,6 +299,27 @@ int fw_walk(const fw_graph* g, fw_algo algo, const fw_params* params, const uint
   return fw_walk_ex(g, algo, params, starts, n, length, seed, out_paths, nullptr);
 }
 
+int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32_t* starts,
+                uint64_t n, uint32_t length, uint64_t seed, void* stream, fw_tune* best) {
+  fw::DevParams dp;
+  int rc = fw::check_walk_args(g, (int)algo, params, n, length, starts, starts, &dp);
+  if (rc) return rc;
+  if (n == 0) return fw::set_error(FW_EINVAL, "empty sample");
+  fw::TuneCfg c;
+  rc = fw::autotune(g, (int)algo, dp, starts, n, length, seed, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  if (best) {
+    std::memset(best, 0, sizeof(*best));
+    best->wg_size = c.wg_size;
+    best->slots = c.slots;
+    best->tiny_max = c.tiny_max;
+    best->hub_min = c.hub_min;
+    best->wgs_per_cu = c.wgs_per_cu;
+    best->hash_cells = c.hash_cells;
+  }
+  return FW_OK;
+}
+
 int fw_sync(const fw_graph* g, void* stream) {
   if (!g) return fail(FW_EINVAL, "graph is NULL");
   return fw::read_status(g, (hipStream_t)stream);

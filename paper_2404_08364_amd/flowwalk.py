@@ -80,6 +80,8 @@ def _bind(lib):
         "fw_walk_ex": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                         ctypes.POINTER(WalkOpts)], i32),
         "fw_sync": ([vp, vp], i32),
+        "fw_autotune": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
+                         ctypes.POINTER(Tune)], i32),
         "fw_server_create": ([vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], i32),
         "fw_server_submit": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64,
                               ctypes.POINTER(u64)], i32),
@@ -232,6 +234,22 @@ def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
                   stream, async_, qid_base, tune, use_graph)
     _check(rc, "fw_walk_ex")
     return out
+
+
+def autotune(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
+             stream=None) -> dict:
+    """Tunes the persistent form on the queries of `starts` (a device tensor
+    holding a sample of the workload) and returns the chosen configuration."""
+    import torch
+    starts = starts.contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream(starts.device)
+    best = Tune()
+    a = ALGOS.get(algo, algo)
+    _check(_lib.fw_autotune(graph.handle, a, None if prm is None else ctypes.byref(prm),
+                            starts.data_ptr(), starts.shape[0], length, seed,
+                            _stream_handle(stream), ctypes.byref(best)), "fw_autotune")
+    return {k: getattr(best, k) for k, _ in Tune._fields_}
 
 
 def sync(graph: Graph, stream=None):

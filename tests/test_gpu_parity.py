@@ -241,3 +241,19 @@ def test_async_on_stream_and_qid_base(env, powerlaw):
     exp = oracle.walk(g, "metapath", oracle.params(schema=[2, 0]), starts, 9, 5,
                       qid_base=123456789)
     assert_rows_equal(out.cpu().numpy().view(np.uint32), exp, "async qid_base")
+
+
+def test_autotune_then_walks_match(env, powerlaw):
+    torch, fw = env
+    g = powerlaw
+    G = fw.Graph.of(g)
+    prm = fw.make_params((1, 2, 4))
+    starts = np.arange(g.n_vertices, dtype=np.uint32)[::3]
+    st = torch.from_numpy(starts.astype(np.int32)).cuda()
+    best = fw.autotune(G, "node2vec", prm, st[::4].contiguous(), 10, 1)
+    assert best["wgs_per_cu"] >= 1 and best["hash_cells"] >= 64 and best["tiny_max"] <= 16
+    for mode in ("auto", "persistent"):
+        got = fw.walk(G, "node2vec", prm, st, 10, 4, mode=mode)
+        torch.cuda.synchronize()
+        exp = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts, 10, 4)
+        assert_rows_equal(got.cpu().numpy().view(np.uint32), exp, f"after autotune {mode}")
