@@ -95,6 +95,17 @@ __device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x) {
   return x;
 }
 
+// Maximum over the 64 lanes (returned in every lane).
+__device__ __forceinline__ uint32_t wave_max32(uint32_t x) {
+  x = max(x, dpp32<0x111, 0xF>(x));
+  x = max(x, dpp32<0x112, 0xF>(x));
+  x = max(x, dpp32<0x114, 0xF>(x));
+  x = max(x, dpp32<0x118, 0xF>(x));
+  x = max(x, dpp32<0x142, 0xA>(x));
+  x = max(x, dpp32<0x143, 0xC>(x));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);

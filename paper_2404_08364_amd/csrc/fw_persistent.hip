@@ -14,12 +14,13 @@
 // There are no workgroup barriers: wavefronts never wait for each other, so
 // every resident wavefront keeps its loads in flight.
 //
-// Node2vec membership in N(prev) for non-tiny hops uses a per-wavefront LDS
-// structure built for the hop: an exact 4-cell-bucket hash set when N(prev)
-// fits, else a one-bit-per-hash filter whose set bits are confirmed by binary
-// search of the sorted row in global memory; when N(prev) is much larger than
-// N(cur), plain binary search.  No global memory beyond the inputs, the
-// output paths and one head counter is used.
+// Node2vec membership in N(prev) for non-tiny hops uses the wavefront's LDS
+// region: an exact 4-cell-bucket hash set of N(prev) when it fits; otherwise,
+// while N(prev) is at most 8x N(cur), a merge of the two sorted rows (each
+// 256-entry chunk of N(cur) stages the window of N(prev) that holds its value
+// range into LDS and searches it there); when N(prev) is much larger than
+// N(cur), binary search of the sorted row in global memory.  No global memory
+// beyond the inputs, the output paths and one head counter is used.
 #include <cstring>
 
 #include "fw_kernels.h"
@@ -52,9 +53,8 @@ __device__ __forceinline__ bool has4(uint4 v, uint32_t u) {
 //      fw_dyn_lds[base, base + 4 nb), kEnd marks an empty cell; a key lives
 //      in the first bucket, in probe order from its hash, that had a free cell
 //      when it was inserted, so a lookup stops at a hit or at a bucket with a
-//      free cell;
-//   2  one-bit filter in LDS (bit hash(x) set for every x in N(prev)): a clear
-//      bit proves absence, a set bit is confirmed by binary search.
+//      free cell.
+// (Mode 2, the merge of sorted rows, has its own pass: merge_group_totals.)
 // One type for all modes keeps a single copy of the sampler in the kernel.
 struct MemberAny {
   int mode;
@@ -104,26 +104,14 @@ struct MemberAny {
       }
       return;
     }
-    if (mode == 2) {
-      // Filter: only keys whose bit is set are searched (few of them).
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t h = (u[j] * kFib) >> shift;
-        hit[j] = (fw_dyn_lds[base + (h >> 5)] >> (h & 31)) & 1u;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (hit[j]) hit[j] = row_contains(adj, po, pd, u[j]);
-      return;
-    }
     row_contains4(adj, po, pd, u, hit);
   }
 };
 
 struct Table {
   uint32_t base, cells;   // this wavefront's LDS region
-  uint32_t bmask, shift;  // geometry of what was built
-  int kind;               // 0: none (global search), 1: hash set, 2: filter
+  uint32_t bmask, shift;  // geometry of the hash set
+  int kind;               // 0: global search, 1: hash set, 2: merge of sorted rows
   uint64_t po, pd;        // N(prev)
 };
 
@@ -132,48 +120,155 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Builds the membership structure of N(prev) for one node2vec hop from a
-// vertex of degree d, with the 64 lanes of the wavefront.
+// Chooses (and for the hash set builds) the membership structure of N(prev)
+// for one node2vec hop from a vertex of degree d, with the wavefront's lanes.
 __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restrict__ adj,
                                             uint64_t d, int lane) {
   tb.kind = 0;
   if (tb.pd == 0 || tb.pd > 8 * d) return;  // a few searches beat a build
-  if (2 * tb.pd <= tb.cells) {
-    uint32_t bits = log2_ceil((2 * tb.pd + 3) / 4);
-    if (bits < 2) bits = 2;
-    tb.bmask = (1u << bits) - 1;
-    tb.shift = 32 - bits;
-    const uint32_t cells = 4u << bits;
-    for (uint32_t i = lane; i < cells; i += kWave) fw_dyn_lds[tb.base + i] = kEnd;
-    wave_sync_lds();
-    for (uint64_t i = lane; i < tb.pd; i += kWave) {
-      const uint32_t u = adj[tb.po + i];
-      uint32_t b = (u * kFib) >> tb.shift;
-      for (;;) {
-        uint32_t j = 0;
-        for (; j < 4; ++j) {
-          const uint32_t old = atomicCAS(&fw_dyn_lds[tb.base + 4 * b + j], kEnd, u);
-          if (old == kEnd || old == u) break;
-        }
-        if (j < 4) break;
-        b = (b + 1) & tb.bmask;
-      }
-    }
-    wave_sync_lds();
-    tb.kind = 1;
+  if (2 * tb.pd > tb.cells) {
+    // Too large for the hash set: merge the sorted rows (the region must
+    // hold at least one 256-entry staging round).
+    if (tb.cells >= 4 * kWave) tb.kind = 2;
     return;
   }
-  // Filter over all the region's bits (cells * 32 of them).
-  const uint32_t bits = log2_ceil((uint64_t)tb.cells * 32);
+  uint32_t bits = log2_ceil((2 * tb.pd + 3) / 4);
+  if (bits < 2) bits = 2;
+  tb.bmask = (1u << bits) - 1;
   tb.shift = 32 - bits;
-  for (uint32_t i = lane; i < tb.cells; i += kWave) fw_dyn_lds[tb.base + i] = 0u;
+  const uint32_t cells = 4u << bits;
+  for (uint32_t i = lane; i < cells; i += kWave) fw_dyn_lds[tb.base + i] = kEnd;
   wave_sync_lds();
   for (uint64_t i = lane; i < tb.pd; i += kWave) {
-    const uint32_t h = (adj[tb.po + i] * kFib) >> tb.shift;
-    atomicOr(&fw_dyn_lds[tb.base + (h >> 5)], 1u << (h & 31));
+    const uint32_t u = adj[tb.po + i];
+    uint32_t b = (u * kFib) >> tb.shift;
+    for (;;) {
+      uint32_t j = 0;
+      for (; j < 4; ++j) {
+        const uint32_t old = atomicCAS(&fw_dyn_lds[tb.base + 4 * b + j], kEnd, u);
+        if (old == kEnd || old == u) break;
+      }
+      if (j < 4) break;
+      b = (b + 1) & tb.bmask;
+    }
   }
   wave_sync_lds();
-  tb.kind = 2;
+  tb.kind = 1;
+}
+
+// Four lower-bound searches in the sorted LDS run fw_dyn_lds[b, b + n), one
+// trip count for all lanes (n is wave-uniform).
+__device__ __forceinline__ void lds_contains4(uint32_t b, uint32_t n, const uint32_t u[4],
+                                              bool hit[4]) {
+  if (n == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hit[j] = false;
+    return;
+  }
+  uint32_t base[4] = {b, b, b, b};
+  uint32_t len = n;
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = fw_dyn_lds[base[j] + half];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) base[j] = (x[j] < u[j]) ? base[j] + half : base[j];
+    len -= half;
+  }
+  const uint32_t last = b + n - 1;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t x0 = fw_dyn_lds[base[j]];
+    const uint32_t x1 = fw_dyn_lds[min(base[j] + 1, last)];
+    hit[j] = (x0 == u[j]) || (x0 < u[j] && base[j] < last && x1 == u[j]);
+  }
+}
+
+// Pass 1 of a node2vec hop by merging the sorted rows N(cur) and N(prev).
+// Each iteration takes one 64-quad chunk (256 consecutive entries of N(cur),
+// ascending): it stages into LDS the entries of N(prev) from a cursor up to
+// the chunk's largest key, 256 per round, and tests the chunk's keys against
+// that window.  Entries below the largest key cannot match any later key, so
+// the cursor moves past them; a window too large for the region falls back
+// to binary search in global memory for that chunk and for the rest of the
+// pass.  Lane g returns the total of group g (the layout of GroupSplit).
+template <class E>
+__device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSlice& s,
+                                                       const GroupSplit& sp, const Table& tb,
+                                                       int lane) {
+  const uint32_t* __restrict__ pr = ev.adj + tb.po;
+  uint64_t cursor = 0;
+  bool global = false;
+  uint64_t mine = 0;
+  for (uint64_t g = 0; g < sp.groups; ++g) {
+    const uint64_t gb = g * sp.gsz;
+    const uint64_t ge = min(gb + sp.gsz, s.nq);
+    uint64_t acc = 0;
+    for (uint64_t c0 = gb; c0 < ge; c0 += kWave) {
+      const uint64_t q = c0 + lane;
+      const bool valid = q < ge;
+      const uint64_t p = s.a + 4 * (valid ? q : c0);
+      uint32_t wq[4] = {1u, 1u, 1u, 1u};
+      if (ev.w != nullptr) {
+        const uint4 v = *reinterpret_cast<const uint4*>(ev.w + p);
+        wq[0] = v.x; wq[1] = v.y; wq[2] = v.z; wq[3] = v.w;
+      }
+      const uint4 a = *reinterpret_cast<const uint4*>(ev.adj + p);
+      const uint32_t key[4] = {a.x, a.y, a.z, a.w};
+      bool live[4];
+      uint32_t kmax = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        live[j] = valid && p + j >= s.o && p + j < s.o + s.d;
+        if (live[j]) kmax = max(kmax, key[j]);
+      }
+      kmax = wave_max32(kmax);
+      bool in[4] = {false, false, false, false};
+      if (!global) {
+        // Stage N(prev)[cursor, cursor + W): the entries <= kmax (a prefix,
+        // N(prev) being sorted).
+        uint32_t W = 0;
+        uint64_t below = 0;  // staged entries < kmax
+        for (;;) {
+          if (W + 4 * kWave > tb.cells) {  // window larger than the region
+            global = true;
+            break;
+          }
+          uint32_t cnt_le = 0, cnt_lt = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint64_t idx = cursor + W + 4 * lane + j;
+            const uint32_t v = idx < tb.pd ? pr[idx] : kEnd;
+            cnt_le += (idx < tb.pd && v <= kmax) ? 1u : 0u;
+            cnt_lt += (idx < tb.pd && v < kmax) ? 1u : 0u;
+            fw_dyn_lds[tb.base + W + 4 * lane + j] = v;
+          }
+          const uint32_t n_le = (uint32_t)wave_sum(cnt_le);
+          below += wave_sum(cnt_lt);
+          W += n_le;
+          if (n_le < 4 * kWave) break;
+        }
+        wave_sync_lds();
+        if (!global) {
+          lds_contains4(tb.base, W, key, in);
+          cursor += below;
+        }
+        wave_sync_lds();
+      }
+      if (global) row_contains4(ev.adj, tb.po, tb.pd, key, in);
+      const uint32_t d_in = ev.f_in - ev.f_out, d_ret = ev.f_ret - ev.f_out;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool is_ret = key[j] == ev.prev;
+        const uint32_t f = ev.f_out + ((in[j] && !is_ret) ? d_in : 0u) + (is_ret ? d_ret : 0u);
+        acc += live[j] ? (uint64_t)wq[j] * f : 0ull;
+      }
+    }
+    const uint64_t tot = wave_sum(acc);
+    if ((uint64_t)lane == g) mine = tot;
+  }
+  return mine;
 }
 
 template <int ALGO, bool WEIGHTED, class MEM>
@@ -355,14 +450,33 @@ __global__ __launch_bounds__(kBlock) void k_walk_persistent(
       }
       const uint64_t u = philox_draw(R.seed, R.qid_base + qid, t);
       auto ev = base_eval<ALGO, WEIGHTED, MemberAny>(g, prm, o, prev, t);
-      ev.mem.mode = tb.kind;
+      ev.mem.mode = tb.kind == 1 ? 1 : 0;
       ev.mem.base = tb.base;
       ev.mem.bmask = tb.bmask;
       ev.mem.shift = tb.shift;
       ev.mem.adj = g.adj;
       ev.mem.po = tb.po;
       ev.mem.pd = tb.pd;
-      const int64_t idx = wave_pick(ev, o, d, u);
+      int64_t idx;
+      if (ALGO == kNode2Vec && tb.kind == 2) {
+        // Pass 1 by merge; the locate re-evaluates one group with searches.
+        const QuadSlice qs(o, d);
+        const GroupSplit sp(qs.nq);
+        const uint64_t mine = merge_group_totals(ev, qs, sp, tb, lane);
+        const uint64_t incl = wave_incl_scan(mine);
+        const uint64_t total = readlane64(incl, kWave - 1);
+        idx = -1;
+        if (total != 0) {
+          uint64_t r = scale_draw(u, total);
+          const uint64_t m = ballot(incl > r);
+          const int gs = m ? first_lane(m) : (int)sp.groups - 1;
+          r -= readlane64(incl - mine, gs);
+          const uint64_t lo = (uint64_t)gs * sp.gsz;
+          idx = (int64_t)wave_locate(ev, qs, lo, min(sp.gsz, qs.nq - lo), r);
+        }
+      } else {
+        idx = wave_pick(ev, o, d, u);
+      }
       uint32_t* row = R.out + qid * ((uint64_t)length + 1);
       const bool mine = grp == src / kGroupLanes;
       if (idx < 0) {

@@ -217,7 +217,7 @@ RECIPES = {
     ),
     # Chung-Lu gamma=2.0 shaped like a 227M-vertex / 2.71B-edge social graph.
     "chunglu227m_n2v": dict(
-        graph=dict(kind="chung_lu", n=227_000_000, draws=1_500_000_000, gamma=2.0, i0=60.0,
+        graph=dict(kind="chung_lu", n=227_000_000, draws=1_620_000_000, gamma=2.0, i0=30.0,
                    seed=227),
         weights=dict(kind="uniform", lo=1, hi=1000, seed=22701),
         labels=None,

@@ -143,6 +143,7 @@ STAGED_TUNES = [
 
 PERSISTENT_TUNES = [
     dict(tiny_max=1, wgs_per_cu=1, hash_cells=64),
+    dict(tiny_max=2, wgs_per_cu=2, hash_cells=512),
     dict(tiny_max=4, wgs_per_cu=3, hash_cells=256),
     dict(tiny_max=16, wgs_per_cu=4, hash_cells=1024),
     dict(tiny_max=16, wgs_per_cu=8, hash_cells=4096),
@@ -198,6 +199,19 @@ def test_hub_to_hub_membership(env, mode, d):
     starts = np.array([0, 1] * 64 + list(range(2, min(200, d + 2))), dtype=np.uint32)
     _check(env, g, "node2vec", (4, 2, 1), (), starts, 12, 5, mode)
     _check(env, g, "node2vec", (1, 2, 4), (), starts, 12, 6, mode)
+
+
+@pytest.mark.parametrize("cells", [256, 512, 1024, 4096])
+@pytest.mark.parametrize("d", [700, 3000, 40000])
+def test_merge_membership_windows(env, cells, d):
+    """Hub-to-hub hops whose N(prev) exceeds the hash set: the merge of the
+    sorted rows, with windows that fit, that need several staging rounds, and
+    that overflow the region (falling back to global search)."""
+    torch, fw = env
+    g = _two_hubs(d)
+    starts = np.array([0, 1] * 128, dtype=np.uint32)
+    _check(env, g, "node2vec", (4, 2, 1), (), starts, 9, 11, "persistent",
+           tune=fw.make_tune(hash_cells=cells, tiny_max=1))
 
 
 def test_graph_replay_matches_eager(env, powerlaw):
