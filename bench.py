@@ -54,10 +54,15 @@ def byte_model(algo: str, weighted: bool, labelled: bool):
     return dict(scan=(1 + (4 if weighted else 0)), emit=8)
 
 
+# Sources the persistent walker kernel is compiled from (and its build flags).
+WALKER_SOURCES = ["csrc/fw_device.h", "csrc/fw_wave_sampler.h", "csrc/fw_kernels.h",
+                  "csrc/fw_persistent.hip", "build.py"]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha1()
-    for p in sorted((ROOT / "paper_2404_08364_amd" / "csrc").glob("*")):
-        h.update(p.read_bytes())
+    for rel in WALKER_SOURCES:
+        h.update((ROOT / "paper_2404_08364_amd" / rel).read_bytes())
     return h.hexdigest()[:12]
 
 
@@ -81,11 +86,15 @@ def oracle_params(prm, algo):
 
 
 def account(torch, paths, deg, model):
-    """Realised hops, attempted hops and algorithmic bytes of one pass."""
+    """Realised hops, attempted hops, scanned neighbours and algorithmic bytes
+    of one pass; `prev_bytes` is what reading N(prev) once per node2vec hop
+    (t >= 1: its two offsets and its adjacency slice) would add."""
     L = paths.shape[1] - 1
     hops = 0
     attempts = 0
     scanned = 0
+    prev_scanned = 0
+    prev_hops = 0
     for t in range(L):
         cur = paths[:, t]
         live = cur != -1
@@ -95,8 +104,44 @@ def account(torch, paths, deg, model):
         attempts += n_live
         scanned += int(deg[cur[live].long()].sum())
         hops += int((paths[:, t + 1] != -1).sum())
+        if t >= 1:
+            prev_hops += n_live
+            prev_scanned += int(deg[paths[:, t - 1][live].long()].sum())
     total = attempts * 16 + scanned * model["scan"] + hops * model["emit"]
-    return hops, attempts, scanned, total
+    return dict(hops=hops, attempts=attempts, scanned=scanned, bytes=total,
+                prev_bytes=prev_hops * 16 + prev_scanned * 4)
+
+
+def device_facts(torch, dev):
+    """What the runtime reports for the device (hipGetDeviceProperties)."""
+    p = torch.cuda.get_device_properties(dev)
+    facts = dict(name=p.name, compute_units=p.multi_processor_count,
+                 hbm_bytes=p.total_memory)
+    for k in ("gcnArchName", "L2_cache_size", "max_threads_per_multi_processor",
+              "warp_size", "shared_memory_per_block", "clock_rate"):
+        v = getattr(p, k, None)
+        if v is not None:
+            facts[k] = v
+    return facts
+
+
+def copy_bandwidth(torch, dev, nbytes=2 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes per second), median of
+    `reps` timed copies: the achievable streaming bandwidth on this device."""
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (float(np.median(ms)) / 1e3) / 1e9
 
 
 def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
@@ -116,74 +161,96 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
     wall = time.perf_counter() - t0
     hops = int((rows[:, 1:] != oracle.END).sum())
     ok = bool(np.array_equal(gpu_rows_fn(qids), rows))
+    # One host thread on a sixth of that sample (every 6th of its queries).
+    q1 = qids[::6]
+    t0 = time.perf_counter()
+    rows1 = oracle.walk_ids(g, algo, oprm, starts, q1, L, seed)
+    wall1 = time.perf_counter() - t0
+    hops1 = int((rows1[:, 1:] != oracle.END).sum())
     return dict(value=hops / wall, unit="walk steps/s", cores=threads, kind="oracle",
                 sample=f"{len(qids)} queries (every {step}-th query id), {hops} hops, "
                        f"{wall:.1f} s wall on {threads} host threads",
-                parity_on_sample=ok)
+                parity_on_sample=ok,
+                one_core=dict(value=hops1 / wall1, queries=len(q1), hops=hops1,
+                              seconds=wall1))
 
 
-def serve_phase(fw, synth, workload: str, seconds: float, rate: float, budget: int, log):
-    """Poisson request stream against the served form; returns latency and
-    throughput figures.  Latency = completion (server clock) minus the
+def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
+                budget: int, log):
+    """Poisson request streams against the served form, one per offered rate
+    (each for `seconds`, capped at `max_requests` requests); returns latency
+    and throughput per rate.  Latency = completion (server clock) minus the
     request's scheduled arrival time (both CLOCK_MONOTONIC)."""
     import threading
     g = synth.load_recipe_graph(workload)
     G = fw.Graph.of(g)
-    rng = np.random.default_rng(2024)
-    n_req = int(seconds * rate)
-    gaps = rng.exponential(1.0 / rate, n_req)
-    arrivals = np.cumsum(gaps)
-    sizes = np.floor(np.exp(rng.uniform(0, np.log(65536), n_req))).astype(np.int64)
-    kinds = rng.integers(0, 3, n_req)
-    lengths = rng.integers(10, 81, n_req)
-    seeds = rng.integers(0, 1 << 62, n_req)
     params = [(("deepwalk"), None),
               ("node2vec", fw.make_params(fw.node2vec_factors(2, 1, 1, 2))),
               ("metapath", fw.make_params(schema=[0, 1, 2]))]
-    starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
-    srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=4, max_batch_requests=512)
-    tickets = [None] * n_req
-    sched_ns = [0] * n_req
-    lat = np.zeros(n_req)
-    hops = np.zeros(n_req, dtype=np.int64)
+    out = []
+    for k, rate in enumerate(rates):
+        rng = np.random.default_rng(2024 + k)
+        n_req = max(1, min(max_requests, int(seconds * rate)))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        sizes = np.floor(np.exp(rng.uniform(0, np.log(65536), n_req))).astype(np.int64)
+        kinds = rng.integers(0, 3, n_req)
+        lengths = rng.integers(10, 81, n_req)
+        seeds = rng.integers(0, 1 << 62, n_req)
+        starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77 + k)
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=4, max_batch_requests=512)
+        tickets = [None] * n_req
+        sched_ns = [0] * n_req
+        lat = np.zeros(n_req)
+        hops = np.zeros(n_req, dtype=np.int64)
 
-    def submitter(t0):
-        for i in range(n_req):
-            target = t0 + int(arrivals[i] * 1e9)
-            now = time.monotonic_ns()
-            if target > now:
-                time.sleep((target - now) / 1e9)
-            algo, prm = params[kinds[i]]
-            sched_ns[i] = target
-            tickets[i] = srv.submit(algo, prm, starts_all[offs[i]:offs[i + 1]],
-                                    int(lengths[i]), int(seeds[i]))
+        def submitter(t0):
+            for i in range(n_req):
+                target = t0 + int(arrivals[i] * 1e9)
+                now = time.monotonic_ns()
+                if target > now:
+                    time.sleep((target - now) / 1e9)
+                algo, prm = params[kinds[i]]
+                sched_ns[i] = target
+                tickets[i] = srv.submit(algo, prm, starts_all[offs[i]:offs[i + 1]],
+                                        int(lengths[i]), int(seeds[i]))
 
-    t0 = time.monotonic_ns() + 50_000_000
-    th = threading.Thread(target=submitter, args=(t0,))
-    th.start()
-    done = 0
-    while done < n_req:
-        while tickets[done] is None:
-            time.sleep(0.0005)
-        paths, st = srv.wait(tickets[done])
-        lat[done] = (st["done_ns"] - sched_ns[done]) / 1e6
-        hops[done] = int((paths[:, 1:] != 0xFFFFFFFF).sum())
-        done += 1
-    th.join()
-    t_end = time.monotonic_ns()
-    srv.close()
+        t0 = time.monotonic_ns() + 50_000_000
+        th = threading.Thread(target=submitter, args=(t0,))
+        th.start()
+        done = 0
+        while done < n_req:
+            while tickets[done] is None:
+                time.sleep(0.0005)
+            paths, st = srv.wait(tickets[done])
+            lat[done] = (st["done_ns"] - sched_ns[done]) / 1e6
+            hops[done] = int((paths[:, 1:] != 0xFFFFFFFF).sum())
+            done += 1
+        th.join()
+        t_end = time.monotonic_ns()
+        srv.close()
+        wall = (t_end - t0) / 1e9
+        span = float(arrivals[-1])
+        offered = float(hops.sum()) / span if span > 0 else float("nan")
+        served = float(hops.sum()) / wall
+        r = dict(offered_rate_per_s=rate, requests=n_req, arrival_span_s=span, duration_s=wall,
+                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                 mean_ms=float(lat.mean()), offered_steps_per_s=offered,
+                 served_steps_per_s=served, served_queries=int(sizes.sum()),
+                 keeps_up=bool(wall <= 1.1 * span + 0.5))
+        log(f"serve @ {rate}/s: {r}")
+        out.append(r)
     G.free()
-    wall = (t_end - t0) / 1e9
-    res = dict(workload=workload, requests=n_req, offered_rate_per_s=rate, duration_s=wall,
-               p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-               mean_ms=float(lat.mean()), served_steps_per_s=float(hops.sum() / wall),
-               served_queries=int(sizes.sum()), mem_budget_bytes=budget,
-               request_mix="sizes floor(log-uniform[1,65536]), algorithm uniform over "
-                           "{DeepWalk, node2vec p=2 q=1/2, MetaPath [0,1,2]}, length U{10..80}, "
-                           "Poisson arrivals")
-    log(f"serve: {res}")
-    return res
+    kept = [r for r in out if r["keeps_up"]]
+    head = max(kept, key=lambda r: r["offered_rate_per_s"]) if kept else out[0]
+    return dict(workload=workload, mem_budget_bytes=budget,
+                request_mix="sizes floor(log-uniform[1,65536]), algorithm uniform over "
+                            "{DeepWalk, node2vec p=2 q=1/2, MetaPath [0,1,2]}, length U{10..80}, "
+                            "Poisson arrivals",
+                p50_ms=head["p50_ms"], p99_ms=head["p99_ms"],
+                at_rate_per_s=head["offered_rate_per_s"],
+                note="p50/p99 at the highest offered rate the server kept up with",
+                sweep=out)
 
 
 def main():
@@ -198,9 +265,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--use-graph", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="seconds of arrivals per offered rate (0 = no serve phase)")
+    ap.add_argument("--serve-rates", default="50,100,250,500,2000",
+                    help="offered request rates (requests/s), comma-separated")
+    ap.add_argument("--serve-max-requests", type=int, default=3000)
     ap.add_argument("--serve-workload", default="rmat24_serve")
+    ap.add_argument("--queries", type=int, default=0,
+                    help="time only the first N queries of the workload (0 = all)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
     args = ap.parse_args()
@@ -208,7 +280,7 @@ def main():
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy // 4
-        a = torch.arange(n, dtype=torch.int32, device="cuda")
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -241,6 +313,8 @@ def main():
     algo, prm, walk = recipe_params(fw, recipe)
     L, seed = walk["length"], walk["seed"]
     starts_np = synth.recipe_starts(args.workload, g)
+    if args.queries:
+        starts_np = starts_np[: args.queries]
     n = starts_np.shape[0]
     starts = torch.from_numpy(starts_np.view(np.int32)).to(dev)
     out = torch.empty((n, L + 1), dtype=torch.int32, device=dev)
@@ -281,7 +355,8 @@ def main():
 
     deg = torch.from_numpy(np.diff(np.asarray(g.offsets)).astype(np.int64)).to(dev)
     model = byte_model(algo, g.weights is not None, g.labels is not None)
-    hops, attempts, scanned, alg_bytes = account(torch, out, deg, model)
+    acc = account(torch, out, deg, model)
+    hops, attempts, scanned, alg_bytes = acc["hops"], acc["attempts"], acc["scanned"], acc["bytes"]
     paths_main = out.clone()
     value = hops / (ms_step / 1e3)
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
@@ -294,6 +369,9 @@ def main():
         same = bool(torch.equal(out, paths_main))
         plain = dict(ms_per_step=ms_p, value=hops / (ms_p / 1e3), identical_paths=same)
         log(f"plain: {ms_p:.1f} ms/step, identical={same}")
+
+    copy_gbps = copy_bandwidth(torch, dev)
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
 
     traffic = None
     tfile = ROOT / "profiles" / f"traffic_{args.workload}_{args.mode}.json"
@@ -315,8 +393,9 @@ def main():
     if args.serve_seconds > 0:
         del out
         torch.cuda.empty_cache()
-        latency = serve_phase(fw, synth, args.serve_workload, args.serve_seconds,
-                              args.serve_rate, 4 << 30, log)
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        latency = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
+                              args.serve_max_requests, 4 << 30, log)
 
     res = {
         "metric": METRIC,
@@ -344,6 +423,12 @@ def main():
         "neighbours_scanned": scanned,
         "edges_scanned_per_s": scanned / (kern_ms / 1e3),
         "algorithmic_bytes_per_launch": alg_bytes,
+        "prev_row_bytes_per_launch": acc["prev_bytes"] if algo == "node2vec" else 0,
+        "hbm_gbps_incl_prev_row": ((alg_bytes + acc["prev_bytes"]) / (kern_ms / 1e3) / 1e9
+                                   if algo == "node2vec" else achieved),
+        "copy_gbps": copy_gbps,
+        "traffic_gbps": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
+        "device": device_facts(torch, dev),
         "plain": plain,
         "cpu_baseline": cpu,
         "latency": latency,

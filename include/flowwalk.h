@@ -186,6 +186,17 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
 int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32_t* starts,
                 uint64_t n, uint32_t length, uint64_t seed, void* stream, fw_tune* best);
 
+/* Realised hops of a walk result (Alg. 1: a step is one appended vertex):
+ * the entries of columns 1..length of the n x (length + 1) row-major device
+ * matrix out_paths that are not FW_END, written to *steps (host).  Runs on
+ * `stream` (a hipStream_t, NULL = null stream) after the work already queued
+ * there and blocks until the count is known; allocates 8 bytes of device
+ * memory for the call.  out_paths must hold a completed walk result (column
+ * 0 = the start vertices).  Errors: FW_EINVAL (steps NULL, out_paths NULL
+ * with n * length > 0, size overflow), FW_EHIP. */
+int fw_count_steps(const uint32_t* out_paths, uint64_t n, uint32_t length, void* stream,
+                   uint64_t* steps);
+
 /* Waits for `stream` (a hipStream_t, NULL = null stream) and returns the
  * status that kernels of graph g detected since the last check (FW_EINVAL
  * for a start vertex >= V), clearing it. */

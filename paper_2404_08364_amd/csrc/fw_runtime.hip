@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "flowwalk.h"
+#include "fw_device.h"
 #include "fw_kernels.h"
 #include "fw_runtime.h"
 
@@ -117,6 +118,18 @@ int read_status(const fw_graph* g, hipStream_t stream) {
     return fail(FW_EINVAL, "a start vertex is >= n_vertices");
   }
   return FW_OK;
+}
+
+// Counts the entries of p[0, m) that are not FW_END: one grid-stride pass,
+// wave sums, one 64-bit atomic per wavefront.
+__global__ void k_count_not_end(const uint32_t* __restrict__ p, uint64_t m,
+                                unsigned long long* total) {
+  uint64_t c = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    c += p[i] != FW_END;
+  const uint64_t s = wave_sum(c);
+  if (lane_id() == 0 && s) atomicAdd(total, (unsigned long long)s);
 }
 
 }  // namespace fw
@@ -317,6 +330,37 @@ int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32
     best->wgs_per_cu = c.wgs_per_cu;
     best->hash_cells = c.hash_cells;
   }
+  return FW_OK;
+}
+
+int fw_count_steps(const uint32_t* out_paths, uint64_t n, uint32_t length, void* stream,
+                   uint64_t* steps) {
+  if (!steps) return fail(FW_EINVAL, "steps is NULL");
+  *steps = 0;
+  if (n == 0 || length == 0) return FW_OK;
+  if (!out_paths) return fail(FW_EINVAL, "out_paths is NULL");
+  const uint64_t cols = (uint64_t)length + 1;
+  if (n > UINT64_MAX / cols) return fail(FW_EINVAL, "n * (length + 1) overflows");
+  const uint64_t m = n * cols;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned long long* d_total = nullptr;
+  hipError_t e = hipMalloc(&d_total, sizeof(unsigned long long));
+  if (e != hipSuccess) return hip_fail(e, "allocating the step counter");
+  unsigned long long total = 0;
+  e = hipMemsetAsync(d_total, 0, sizeof(unsigned long long), st);
+  if (e == hipSuccess) {
+    const uint64_t blocks = std::min<uint64_t>((m + 255) / 256, 4096);
+    hipLaunchKernelGGL(fw::k_count_not_end, dim3((unsigned)blocks), dim3(256), 0, st, out_paths,
+                       m, d_total);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&total, d_total, sizeof(total), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(d_total);
+  if (e != hipSuccess) return hip_fail(e, "counting steps");
+  // Column 0 holds the start vertex of every row (never FW_END).
+  *steps = total >= n ? total - n : 0;
   return FW_OK;
 }
 

@@ -80,6 +80,7 @@ def _bind(lib):
         "fw_walk_ex": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                         ctypes.POINTER(WalkOpts)], i32),
         "fw_sync": ([vp, vp], i32),
+        "fw_count_steps": ([vp, u64, u32, vp, ctypes.POINTER(u64)], i32),
         "fw_autotune": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                          ctypes.POINTER(Tune)], i32),
         "fw_server_create": ([vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], i32),
@@ -250,6 +251,19 @@ def autotune(graph: Graph, algo, prm: Params | None, starts, length: int, seed: 
                             starts.data_ptr(), starts.shape[0], length, seed,
                             _stream_handle(stream), ctypes.byref(best)), "fw_autotune")
     return {k: getattr(best, k) for k, _ in Tune._fields_}
+
+
+def count_steps(paths, stream=None) -> int:
+    """Realised hops of a walk result: the entries of columns 1.. of the
+    (n, length + 1) device tensor `paths` that are not END."""
+    import torch
+    paths = paths.contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream(paths.device)
+    out = ctypes.c_uint64(0)
+    _check(_lib.fw_count_steps(paths.data_ptr(), paths.shape[0], paths.shape[1] - 1,
+                               _stream_handle(stream), ctypes.byref(out)), "fw_count_steps")
+    return int(out.value)
 
 
 def sync(graph: Graph, stream=None):

@@ -19,7 +19,9 @@ def declared_symbols():
 def test_header_declares_entry_points():
     syms = declared_symbols()
     for name in ["fw_graph_upload", "fw_graph_free", "fw_walk", "fw_walk_ex", "fw_sync",
-                 "fw_node2vec_factors", "fw_last_error", "fw_graph_info_get"]:
+                 "fw_node2vec_factors", "fw_last_error", "fw_graph_info_get", "fw_autotune",
+                 "fw_count_steps", "fw_server_create", "fw_server_submit", "fw_server_poll",
+                 "fw_server_wait", "fw_server_destroy"]:
         assert name in syms
 
 
@@ -73,3 +75,15 @@ def test_null_arguments():
     assert lib.fw_walk(None, 0, None, None, 0, 0, 0, None) == fw.EINVAL
     assert lib.fw_graph_free(None) == fw.OK
     assert isinstance(lib.fw_last_error(), bytes)
+
+
+def test_count_steps_rejects_null_on_host():
+    """fw_count_steps checks its pointers before any device work."""
+    from paper_2404_08364_amd import flowwalk as fw
+    lib = fw.lib()
+    n = ctypes.c_uint64(7)
+    assert lib.fw_count_steps(None, 4, 3, None, None) == fw.EINVAL
+    assert lib.fw_count_steps(None, 4, 3, None, ctypes.byref(n)) == fw.EINVAL
+    assert lib.fw_count_steps(None, 0, 3, None, ctypes.byref(n)) == fw.OK and n.value == 0
+    assert lib.fw_count_steps(None, 5, 0, None, ctypes.byref(n)) == fw.OK and n.value == 0
+    assert lib.fw_count_steps(None, 1 << 62, 7, None, ctypes.byref(n)) == fw.EINVAL

@@ -84,6 +84,24 @@ def test_powerlaw_graph(env, powerlaw, mode, algo, factors, schema):
     _check(env, g, algo, factors, schema, starts, 12, 31337, mode)
 
 
+@pytest.mark.parametrize("algo,factors,schema", [ALGOS[1], ALGOS[3]])
+def test_count_steps_matches_oracle(env, powerlaw, algo, factors, schema):
+    """fw_count_steps counts exactly the oracle's realised hops (MetaPath
+    walks end early, so the count is below n * length)."""
+    torch, fw = env
+    g = powerlaw
+    starts = np.arange(g.n_vertices, dtype=np.uint32)[::3]
+    G = fw.Graph.of(g)
+    st = torch.from_numpy(starts.view(np.int32)).cuda()
+    out = fw.walk(G, algo, fw.make_params(factors, schema), st, 17, 99, mode="persistent")
+    exp = oracle.walk(g, algo, oracle.params(*factors, schema=schema), starts, 17, 99)
+    want = int((exp[:, 1:] != END).sum())
+    assert fw.count_steps(out) == want
+    assert fw.count_steps(out[:1]) == int((exp[:1, 1:] != END).sum())
+    if algo == "metapath":
+        assert want < starts.shape[0] * 17
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_rmat12_node2vec_full(env, mode):
     """R-MAT scale 12, node2vec p=2 q=1/2 (factors 1, 2, 4), one query per
