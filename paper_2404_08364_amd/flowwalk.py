@@ -98,6 +98,15 @@ def _bind(lib):
     return lib
 
 
+# torch's ROCm wheel ships its own HIP runtime under a different file name.
+# Loading it first lets the dynamic linker resolve this library's HIP
+# dependency to that same copy: two HIP runtimes in one process would each
+# try to own the GPU, and the second would find none.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = _bind(ctypes.CDLL(str(LIB_PATH)))
 
 
