@@ -21,15 +21,16 @@ _LIB = _HERE / "libfworacle.so"
 _lib = None
 
 OK, EINVAL, ENOMEM, EOVERFLOW = 0, -1, -2, -3
-DEEPWALK, NODE2VEC, METAPATH = 0, 1, 2
-ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH}
+DEEPWALK, NODE2VEC, METAPATH, PPR = 0, 1, 2, 3
+ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH, "ppr": PPR}
 END = 0xFFFFFFFF
 
 
 class Params(ctypes.Structure):
     _fields_ = [("f_ret", ctypes.c_uint32), ("f_in", ctypes.c_uint32),
                 ("f_out", ctypes.c_uint32), ("schema_len", ctypes.c_uint32),
-                ("schema", ctypes.c_uint8 * 16)]
+                ("schema", ctypes.c_uint8 * 16),
+                ("stop_num", ctypes.c_uint32), ("stop_den", ctypes.c_uint32)]
 
 
 class _Graph(ctypes.Structure):
@@ -66,6 +67,10 @@ def bind(lib):
     lib.fwo_philox4x64_10.restype = None
     lib.fwo_draw.argtypes = [u64, u64, u64]
     lib.fwo_draw.restype = u64
+    lib.fwo_stop_coin.argtypes = [u64, u32, u32]
+    lib.fwo_stop_coin.restype = i32
+    lib.fwo_stop.argtypes = [u64, u64, u64, u32, u32]
+    lib.fwo_stop.restype = i32
     lib.fwo_scale.argtypes = [u64, u64]
     lib.fwo_scale.restype = u64
     lib.fwo_pick.argtypes = [vp, u64, u64]
@@ -118,9 +123,10 @@ class HostGraph:
         return int(self.c.n_vertices)
 
 
-def params(f_ret=1, f_in=1, f_out=1, schema=()) -> Params:
+def params(f_ret=1, f_in=1, f_out=1, schema=(), stop=(0, 1)) -> Params:
     p = Params()
     p.f_ret, p.f_in, p.f_out = f_ret, f_in, f_out
+    p.stop_num, p.stop_den = stop
     p.schema_len = len(schema)
     for i, s in enumerate(schema):
         p.schema[i] = s
@@ -145,6 +151,14 @@ def philox4x64_10(ctr, key) -> np.ndarray:
 
 def draw(seed: int, qid: int, t: int) -> int:
     return int(_load().fwo_draw(seed, qid, t))
+
+
+def stop_coin(u1: int, stop_num: int, stop_den: int) -> bool:
+    return bool(_load().fwo_stop_coin(u1, stop_num, stop_den))
+
+
+def stop(seed: int, qid: int, t: int, stop_num: int, stop_den: int) -> bool:
+    return bool(_load().fwo_stop(seed, qid, t, stop_num, stop_den))
 
 
 def scale(u: int, total: int) -> int:

@@ -56,6 +56,19 @@ uint64_t fwo_draw(uint64_t seed, uint64_t qid, uint64_t t) {
   return out[0];
 }
 
+int fwo_stop_coin(uint64_t u1, uint32_t stop_num, uint32_t stop_den) {
+  unsigned __int128 p = (unsigned __int128)u1 * stop_den;
+  return (uint64_t)(p >> 64) < stop_num;
+}
+
+int fwo_stop(uint64_t seed, uint64_t qid, uint64_t t, uint32_t stop_num, uint32_t stop_den) {
+  uint64_t ctr[4] = {qid, t, 0, 0};
+  uint64_t key[2] = {seed, 0};
+  uint64_t out[4];
+  fwo_philox4x64_10(ctr, key, out);
+  return fwo_stop_coin(out[1], stop_num, stop_den);
+}
+
 uint64_t fwo_scale(uint64_t u, uint64_t total) {
   unsigned __int128 p = (unsigned __int128)u * total;
   return (uint64_t)(p >> 64);
@@ -131,6 +144,10 @@ static int is_neighbour(const fwo_graph* g, uint32_t v, uint32_t u) {
 static int check_params(const fwo_graph* g, int algo, const fwo_params* p) {
   if (algo == FWO_DEEPWALK) return FWO_OK;
   if (!p) return FWO_EINVAL;
+  if (algo == FWO_PPR) {
+    if (p->stop_den == 0 || p->stop_num > p->stop_den) return FWO_EINVAL;
+    return FWO_OK;
+  }
   if (algo == FWO_NODE2VEC) {
     if (p->f_ret == 0 && p->f_in == 0 && p->f_out == 0) return FWO_EINVAL;
     return FWO_OK;
@@ -147,7 +164,7 @@ static int check_params(const fwo_graph* g, int algo, const fwo_params* p) {
  * neighbour of v', and every other neighbour of v is at distance 2; MetaPath
  * multiplies the weight by Eq. 1, the indicator that the edge label equals
  * the schema label of this hop.  At the first hop node2vec has no v' and uses
- * the weight alone. */
+ * the weight alone.  PPR's transition weights are DeepWalk's. */
 int fwo_transition_weights(const fwo_graph* g, int algo, const fwo_params* p, uint32_t prev,
                            uint32_t cur, uint32_t t, uint64_t* w_out) {
   if (!g || cur >= g->n_vertices) return FWO_EINVAL;
@@ -205,13 +222,18 @@ static uint64_t max_degree(const fwo_graph* g) {
   return m;
 }
 
-/* One query: Algorithm 1's loop with inverse transform sampling. */
+/* One query: Algorithm 1's loop with inverse transform sampling.  A PPR
+ * query first tosses its stop coin at every hop; `length` caps its hops. */
 static int walk_one(const fwo_graph* g, int algo, const fwo_params* p, uint32_t start,
                     uint64_t qid, uint32_t length, uint64_t seed, uint64_t* wbuf,
                     uint32_t* row) {
   if (start >= g->n_vertices) return FWO_EINVAL;
   row[0] = start;
   for (uint32_t t = 0; t < length; ++t) {
+    if (algo == FWO_PPR && fwo_stop(seed, qid, t, p->stop_num, p->stop_den)) {
+      for (uint32_t s = t + 1; s <= length; ++s) row[s] = FWO_END;
+      return FWO_OK;
+    }
     uint32_t cur = row[t];
     uint32_t prev = t > 0 ? row[t - 1] : FWO_END;
     uint64_t b = g->offsets[cur], d = g->offsets[cur + 1] - b;

@@ -1,4 +1,4 @@
-/* CPU oracle for dynamic-graph random walks (DeepWalk, node2vec, MetaPath).
+/* CPU oracle for graph random walks (DeepWalk, node2vec, MetaPath, PPR).
  *
  * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, single-threaded
  * definition that the HIP library is checked against, bit for bit.  Only the
@@ -16,6 +16,10 @@
  * (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
  * SC 2011).  Both the reservoir samplers of section 4 (Propositions 1 and 2)
  * and this pick select neighbour i with probability w'_i / sum(w').
+ *
+ * PPR (the personalized-PageRank walk of the experiments, section 6.1) moves
+ * like weighted DeepWalk but ends before each hop with a fixed stop chance;
+ * the coin is word 1 of the hop's Philox block, the draw stays word 0.
  */
 #ifndef FW_ORACLE_H
 #define FW_ORACLE_H
@@ -35,6 +39,7 @@ extern "C" {
 #define FWO_DEEPWALK 0
 #define FWO_NODE2VEC 1
 #define FWO_METAPATH 2
+#define FWO_PPR 3
 
 #define FWO_END 0xFFFFFFFFu /* path padding after an early end */
 
@@ -48,12 +53,14 @@ typedef struct {
   const uint8_t* labels;
 } fwo_graph;
 
-/* Integer node2vec factors (return, in-out: stay near prev, move away) and
- * the MetaPath label schema, cycled: hop t uses schema[t mod schema_len]. */
+/* Integer node2vec factors (return, in-out: stay near prev, move away), the
+ * MetaPath label schema, cycled: hop t uses schema[t mod schema_len], and
+ * PPR's stop chance stop_num / stop_den (0 <= stop_num <= stop_den, 0 < stop_den). */
 typedef struct {
   uint32_t f_ret, f_in, f_out;
   uint32_t schema_len;
   uint8_t schema[16];
+  uint32_t stop_num, stop_den;
 } fwo_params;
 
 /* Philox4x64 with 10 rounds; out[0..3] for counter ctr[0..3], key key[0..1]. */
@@ -62,6 +69,15 @@ void fwo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 /* The step draw: word 0 of Philox4x64-10(counter = (qid, t, 0, 0),
  * key = (seed, 0)). */
 uint64_t fwo_draw(uint64_t seed, uint64_t qid, uint64_t t);
+
+/* PPR's coin on a uniform 64-bit word u1: 1 (stop) when
+ * floor(u1 * stop_den / 2^64) < stop_num, i.e. with chance stop_num / stop_den
+ * up to 2^-64. */
+int fwo_stop_coin(uint64_t u1, uint32_t stop_num, uint32_t stop_den);
+
+/* Does PPR query qid stop before hop t?  The coin on word 1 of
+ * Philox4x64-10(counter = (qid, t, 0, 0), key = (seed, 0)). */
+int fwo_stop(uint64_t seed, uint64_t qid, uint64_t t, uint32_t stop_num, uint32_t stop_den);
 
 /* floor(u * total / 2^64): maps a uniform 64-bit word to [0, total). */
 uint64_t fwo_scale(uint64_t u, uint64_t total);

@@ -302,7 +302,110 @@ def pin_zero_length_and_dead_ends():
     assert (rows[:, 3] != END).any()
 
 
+def _stop_threshold(num, den):
+    """PPR's coin stops exactly for the words u1 with u1 * den < num * 2^64,
+    i.e. u1 < ceil(num * 2^64 / den) (Python integers)."""
+    return -(-(num << 64) // den)
+
+
+def pin_stop_coin_closed_form():
+    rng = np.random.default_rng(5)
+    for num, den in [(1, 5), (0, 1), (1, 1), (3, 7), (M64 >> 32, M64 >> 32), (1, M64 >> 32),
+                     (4, 5), (123456, 999999)]:
+        c = _stop_threshold(num, den)
+        for u in {0, 1, c - 1, c, c + 1, M64, M64 - 1}:
+            if 0 <= u <= M64:
+                assert oracle.stop_coin(u, num, den) == (u < c), (num, den, u, c)
+        for u in rng.integers(0, 1 << 63, 50, dtype=np.uint64):
+            u = int(u) * 2 + 1
+            assert oracle.stop_coin(u, num, den) == (u < c), (num, den, u)
+
+
+def pin_stop_keying(cases=100):
+    """PPR's coin is word 1 of the block at counter (qid, t, 0, 0), key
+    (seed, 0) (numpy's Philox), the step draw word 0 of the same block."""
+    rng = np.random.default_rng(13)
+    for _ in range(cases):
+        seed, qid, t = (int(x) for x in rng.integers(0, 1 << 40, 3))
+        t %= 1000
+        num, den = (1, 5) if qid % 2 else (2, 3)
+        block = _numpy_philox_block([qid, t, 0, 0], [seed, 0])
+        assert oracle.stop(seed, qid, t, num, den) == (block[1] < _stop_threshold(num, den))
+        assert oracle.draw(seed, qid, t) == block[0]
+
+
+def _python_ppr_walk(g, dist, start, qid, length, seed, stop):
+    """A PPR walk rebuilt from independent parts: numpy's Philox (word 1 for
+    the coin, word 0 for the draw), Python integers, DeepWalk chances."""
+    from helpers import chances
+    c = _stop_threshold(*stop)
+    row = [start]
+    for t in range(length):
+        block = _numpy_philox_block([qid, t, 0, 0], [seed, 0])
+        if block[1] < c:
+            return row + [END] * (length - t)
+        ch = chances(g, dist, "deepwalk", row[-1], None, t)
+        tot = sum(ch)
+        if tot == 0:
+            return row + [END] * (length - t)
+        r = (block[0] * tot) >> 64
+        acc = 0
+        for i, ci in enumerate(ch):
+            acc += ci
+            if acc > r:
+                break
+        row.append(int(g.adj[int(g.offsets[row[-1]]) + i]))
+    return row
+
+
+def pin_ppr_rebuilt():
+    from helpers import hop_distances
+    g, _ = tiny6()
+    dist = hop_distances(g)
+    seed, L, base = 987654321, 9, 77
+    starts = np.arange(60, dtype=np.uint32) % 6
+    for stop in [(1, 5), (1, 2), (2, 7)]:
+        rows = oracle.walk(g, "ppr", oracle.params(stop=stop), starts, L, seed, qid_base=base)
+        for i, s in enumerate(starts):
+            exp = _python_ppr_walk(g, dist, int(s), base + i, L, seed, stop)
+            assert rows[i].tolist() == exp, (stop, i, rows[i], exp)
+
+
+def pin_ppr_length_distribution(n=200_000):
+    """On a graph with no dead end the number of hops is geometric: k hops
+    with chance (1 - a)^k a below the cap L, and (1 - a)^L at the cap."""
+    from fractions import Fraction
+    from scipy.stats import chisquare
+    nv = 12
+    edges = {tuple(sorted((i, (i + s) % nv))) for i in range(nv) for s in (1, 2, 5)}
+    g = csr_from_edges(nv, [(u, v, 1 + (u * v) % 4, 0) for (u, v) in sorted(edges)])
+    L, a = 12, Fraction(1, 5)
+    rows = oracle.walk(g, "ppr", oracle.params(stop=(1, 5)), np.zeros(n, np.uint32), L, 4242)
+    hops = (rows[:, 1:] != END).sum(axis=1)
+    # the hops present form a prefix
+    assert all((rows[i, 1:hops[i] + 1] != END).all() for i in range(0, n, 997))
+    counts = np.bincount(hops, minlength=L + 1)
+    exp = [float((1 - a) ** k * a) * n for k in range(L)] + [float((1 - a) ** L) * n]
+    assert chisquare(counts, exp).pvalue > 1e-4, counts
+
+
+def pin_ppr_limits():
+    """Stop chance 0 is weighted DeepWalk bit for bit; stop chance 1 ends
+    every query before its first hop; bad stop fractions are rejected."""
+    g, _ = tiny6()
+    starts = np.arange(6, dtype=np.uint32).repeat(40)
+    a = oracle.walk(g, "deepwalk", oracle.params(), starts, 10, 31)
+    b = oracle.walk(g, "ppr", oracle.params(stop=(0, 3)), starts, 10, 31)
+    assert np.array_equal(a, b)
+    c = oracle.walk(g, "ppr", oracle.params(stop=(3, 3)), starts, 10, 31)
+    assert (c[:, 0] == starts).all() and (c[:, 1:] == END).all()
+    for stop in [(1, 0), (4, 3)]:
+        rc, _ = oracle.walk_status(g, "ppr", oracle.params(stop=stop), starts, 3, 1)
+        assert rc == oracle.EINVAL, stop
+
+
 ALL_PINS = [pin_philox_kat, pin_philox_numpy, pin_draw_keying, pin_scale_closed_form,
             pin_pick_bruteforce, pin_hand_weights, pin_walk_rebuilt, pin_chi2_paths, pin_identities,
             pin_regular_uniform, pin_path_graph_edges, pin_errors,
-            pin_zero_length_and_dead_ends]
+            pin_zero_length_and_dead_ends, pin_stop_coin_closed_form, pin_stop_keying,
+            pin_ppr_rebuilt, pin_ppr_length_distribution, pin_ppr_limits]

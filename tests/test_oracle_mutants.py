@@ -23,6 +23,11 @@ MUTANTS = {
     "philox_rounds": ("round < 10", "round < 9"),
     "scale_bias": ("(unsigned __int128)u * total", "(unsigned __int128)(u >> 1) * total"),
     "drop_weight": ("w_out[i] = w * f;", "w_out[i] = f;"),
+    "ppr_coin_word": ("return fwo_stop_coin(out[1], stop_num, stop_den);",
+                      "return fwo_stop_coin(out[0], stop_num, stop_den);"),
+    "ppr_coin_le": ("(uint64_t)(p >> 64) < stop_num;", "(uint64_t)(p >> 64) <= stop_num;"),
+    "ppr_coin_hop": ("fwo_stop(seed, qid, t, p->stop_num", "fwo_stop(seed, qid, t + 1, p->stop_num"),
+    "ppr_first_coin": ("if (algo == FWO_PPR && fwo_stop(", "if (algo == FWO_PPR && t > 0 && fwo_stop("),
     "padding": ("for (uint32_t s = t + 1; s <= length; ++s)", "for (uint32_t s = t + 1; s < length; ++s)"),
 }
 
