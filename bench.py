@@ -39,6 +39,8 @@ WORKLOADS = {
     "chunglu24_metapath": "Chung-Lu 2^24 vertices, gamma 2.1, ~253M stored edges, d_max ~0.94M; "
                           "labels U{0..4}, no weights; MetaPath schema [0,1,2,3,4] cycled; one "
                           "query per vertex (16,777,216), 20 hops",
+    "rmat22_ppr": "same graph as rmat22_n2v; PPR with stop chance 1/5 per hop, all 4,194,304 "
+                  "queries from the vertex of largest degree, at most 80 hops",
     "chunglu227m_n2v": "Chung-Lu 227M vertices, gamma 2.0, ~2.7B stored edges; weights U[1,1000]; "
                        "node2vec p=1/2 q=2 (factors 4,2,1); 10M uniform starts, 80 hops",
 }
@@ -47,8 +49,9 @@ WORKLOADS = {
 # attempted hop from v of degree d, offsets (16 B) plus `scan` bytes per
 # neighbour; per realised hop, `emit` more bytes.
 def byte_model(algo: str, weighted: bool, labelled: bool):
-    if algo == "deepwalk":
-        return dict(scan=4 if weighted else 0, emit=8)
+    if algo in ("deepwalk", "ppr"):
+        # PPR's stop coin reads nothing: only hops that move are counted.
+        return dict(scan=4 if weighted else 0, emit=8, moving_only=algo == "ppr")
     if algo == "node2vec":
         return dict(scan=8 if weighted else 4, emit=4)
     return dict(scan=(1 + (4 if weighted else 0)), emit=8)
@@ -74,6 +77,8 @@ def recipe_params(fw, recipe):
         return algo, fw.make_params(fw.node2vec_factors(pn, pd, qn, qd)), walk
     if algo == "metapath":
         return algo, fw.make_params(schema=walk["schema"]), walk
+    if algo == "ppr":
+        return algo, fw.make_params(stop=tuple(walk["stop"])), walk
     return algo, None, walk
 
 
@@ -82,7 +87,8 @@ def oracle_params(prm, algo):
     if prm is None:
         return oracle.params()
     return oracle.params(prm.f_ret, prm.f_in, prm.f_out,
-                         schema=list(prm.schema)[:prm.schema_len])
+                         schema=list(prm.schema)[:prm.schema_len],
+                         stop=(prm.stop_num, prm.stop_den))
 
 
 def account(torch, paths, deg, model):
@@ -101,9 +107,12 @@ def account(torch, paths, deg, model):
         n_live = int(live.sum())
         if n_live == 0:
             break
-        attempts += n_live
+        moved = paths[:, t + 1] != -1
+        if model.get("moving_only"):
+            live = moved
+        attempts += int(live.sum())
         scanned += int(deg[cur[live].long()].sum())
-        hops += int((paths[:, t + 1] != -1).sum())
+        hops += int(moved.sum())
         if t >= 1:
             prev_hops += n_live
             prev_scanned += int(deg[paths[:, t - 1][live].long()].sum())

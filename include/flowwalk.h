@@ -24,8 +24,14 @@
  *                previous vertex and uses w_i alone.
  *   FW_METAPATH  Eq. 1 times w_i: w_i if label_i == schema[t mod schema_len],
  *                else 0.
+ *   FW_PPR       the personalized-PageRank walk of the experiments (section
+ *                6.1): w'_i = w_i, and before every hop the query stops
+ *                with chance stop_num / stop_den, tossed on word 1 of the
+ *                same Philox block: it stops when
+ *                floor(word1 * stop_den / 2^64) < stop_num.  `length` caps
+ *                its hops.
  * A hop whose total T is 0 (no neighbours, or every neighbour masked) ends
- * the walk; the remaining entries of its row are FW_END.
+ * the walk, as does a PPR stop; the remaining entries of its row are FW_END.
  *
  * Conventions.  Every function returns an int status (FW_OK or a negative
  * FW_E* code) and never throws.  fw_last_error() gives a message for the
@@ -53,7 +59,7 @@ extern "C" {
 
 #define FW_END 0xFFFFFFFFu /* path entry after an early end */
 
-typedef enum { FW_DEEPWALK = 0, FW_NODE2VEC = 1, FW_METAPATH = 2 } fw_algo;
+typedef enum { FW_DEEPWALK = 0, FW_NODE2VEC = 1, FW_METAPATH = 2, FW_PPR = 3 } fw_algo;
 
 /* Host CSR view (section 2.1: G = (V, E), N(v), d(v)).
  *   offsets  host, uint64[n_vertices + 1], offsets[0] = 0, non-decreasing,
@@ -70,11 +76,14 @@ typedef struct fw_csr {
 
 /* Algorithm parameters.  f_ret, f_in, f_out: node2vec integer factors (see
  * fw_node2vec_factors); not all zero.  schema[0 .. schema_len): MetaPath
- * label schema, 1 <= schema_len <= 16, cycled. */
+ * label schema, 1 <= schema_len <= 16, cycled.  stop_num / stop_den: PPR's
+ * stop chance per hop, 0 <= stop_num <= stop_den, stop_den > 0 (the
+ * experiments use 1/5). */
 typedef struct fw_params {
   uint32_t f_ret, f_in, f_out;
   uint32_t schema_len;
   uint8_t schema[16];
+  uint32_t stop_num, stop_den;
 } fw_params;
 
 typedef struct fw_graph fw_graph; /* opaque device-resident graph */
@@ -114,10 +123,11 @@ int fw_node2vec_factors(uint32_t p_num, uint32_t p_den, uint32_t q_num, uint32_t
  *   out_paths  device, uint32[n * (length + 1)], row-major: row i receives
  *              the start and then one vertex per hop, FW_END after an early
  *              end.  length = 0 gives rows [start].  n = 0 is a no-op.
- *   params     ignored for FW_DEEPWALK (may be NULL)
+ *   params     ignored for FW_DEEPWALK (may be NULL); required otherwise
  * Runs on the null stream and returns when the walks are done.
  * Errors: FW_EINVAL (bad algorithm or parameters, MetaPath on a graph
- * without labels, NULL pointers, a start vertex >= V: then out_paths is
+ * without labels, a PPR stop chance outside [0, 1], NULL pointers, a start
+ * vertex >= V: then out_paths is
  * unspecified), FW_EOVERFLOW, FW_EHIP. */
 int fw_walk(const fw_graph* g, fw_algo algo, const fw_params* params, const uint32_t* starts,
             uint64_t n, uint32_t length, uint64_t seed, uint32_t* out_paths);

@@ -11,7 +11,7 @@ namespace fw {
 constexpr uint32_t kEnd = 0xFFFFFFFFu;
 constexpr int kWave = 64;
 
-enum Algo : int { kDeepWalk = 0, kNode2Vec = 1, kMetaPath = 2 };
+enum Algo : int { kDeepWalk = 0, kNode2Vec = 1, kMetaPath = 2, kPPR = 3 };
 
 struct DevGraph {
   const uint64_t* __restrict__ off;
@@ -25,13 +25,16 @@ struct DevParams {
   uint32_t f_ret, f_in, f_out;
   uint32_t schema_len;
   uint8_t schema[16];
+  uint32_t stop_num, stop_den;  // PPR: stop chance per hop
 };
 
 // ---------------------------------------------------------------------------
 // Step draw: word 0 of Philox4x64-10 (Salmon et al., SC 2011) at counter
 // (qid, t, 0, 0), key (seed, 0).  One draw per hop, no generator state.
+// Word 1 of the same block is PPR's stop coin.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint64_t qid, uint64_t t) {
+__device__ __forceinline__ uint64_t philox_draw2(uint64_t seed, uint64_t qid, uint64_t t,
+                                                 uint64_t& word1) {
   constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
   constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
   uint64_t c0 = qid, c1 = t, c2 = 0, c3 = 0, k0 = seed, k1 = 0;
@@ -46,7 +49,22 @@ __device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint64_t qid, uin
     k0 += kW0;
     k1 += kW1;
   }
+  word1 = c1;
   return c0;
+}
+
+__device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint64_t qid, uint64_t t) {
+  uint64_t unused;
+  return philox_draw2(seed, qid, t, unused);
+}
+
+// PPR: does the query stop before hop t?  True with chance stop_num /
+// stop_den: floor(word1 * stop_den / 2^64) < stop_num.
+__device__ __forceinline__ bool ppr_stops(const DevParams& p, uint64_t seed, uint64_t qid,
+                                          uint64_t t) {
+  uint64_t word1;
+  philox_draw2(seed, qid, t, word1);
+  return __umul64hi(word1, (uint64_t)p.stop_den) < (uint64_t)p.stop_num;
 }
 
 // floor(u * total / 2^64) in [0, total).

@@ -385,6 +385,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_persistent(
     if (s_live) {
       s_o = g.off[s_cur];
       s_d = g.off[s_cur + 1] - s_o;
+      // A PPR stop ends the query like a dead end: the tiny path pads it.
+      if (ALGO == kPPR) {
+        const ReqDesc R = rq.get(s_r);
+        if (ppr_stops(R.prm, R.seed, R.qid_base + s_qid, s_t)) s_d = 0;
+      }
     }
 
     // ---- tiny hops: one per 16-lane group ------------------------------
@@ -535,6 +540,9 @@ static hipError_t launch_any(int algo, const DevGraph& g, const Reqs<MULTI>& rq,
     case kMetaPath:
       return wt ? go<kMetaPath, true>(g, rq, status, head, c, b, stream)
                 : go<kMetaPath, false>(g, rq, status, head, c, b, stream);
+    case kPPR:
+      return wt ? go<kPPR, true>(g, rq, status, head, c, b, stream)
+                : go<kPPR, false>(g, rq, status, head, c, b, stream);
     default:
       return hipErrorInvalidValue;
   }

@@ -1,5 +1,6 @@
 // Plain batch walker: one wavefront per query, queries assigned to
-// wavefronts statically (query q goes to wavefront q mod W).  This is the
+// wavefronts statically (query q goes to wavefront q mod W).  A PPR query
+// tosses its stop coin before each hop.  This is the
 // query-centric baseline that section 5.2 argues against on GPUs; the
 // persistent form (fw_persistent.hip) adds dynamic scheduling.
 #include "fw_kernels.h"
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(256) void k_walk_plain(DevGraph g, DevParams prm,
     uint32_t cur = s, prev = kEnd;
     uint32_t t = 0;
     for (; t < length; ++t) {
+      if (ALGO == kPPR && ppr_stops(prm, seed, qid_base + q, t)) break;
       const uint64_t o = g.off[cur];
       const uint64_t d = g.off[cur + 1] - o;
       Eval<ALGO, WEIGHTED> ev;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(256) void k_walk_plain(DevGraph g, DevParams prm,
       if (ALGO == kMetaPath) ev.want = schema_label(prm, t);
       const uint64_t u = philox_draw(seed, qid_base + q, t);
       int64_t idx;
-      if (ALGO == kDeepWalk && !WEIGHTED) {
+      if ((ALGO == kDeepWalk || ALGO == kPPR) && !WEIGHTED) {
         // All weights 1: the prefix sum at i is i + 1, so the pick is r.
         idx = d ? (int64_t)scale_draw(u, d) : -1;
       } else {
@@ -114,6 +116,9 @@ hipError_t launch_plain(const LaunchArgs& a, hipStream_t stream) {
       break;
     case kMetaPath:
       if (wt) FW_GO(kMetaPath, true); else FW_GO(kMetaPath, false);
+      break;
+    case kPPR:
+      if (wt) FW_GO(kPPR, true); else FW_GO(kPPR, false);
       break;
     default:
       return hipErrorInvalidValue;

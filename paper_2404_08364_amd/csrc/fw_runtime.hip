@@ -66,7 +66,7 @@ int set_error(int code, const char* msg) { return fail(code, msg); }
 int check_walk_args(const fw_graph* g, int algo, const fw_params* params, uint64_t n,
                     uint32_t length, const void* starts, const void* out, DevParams* dp) {
   if (!g) return fail(FW_EINVAL, "graph is NULL");
-  if (algo != FW_DEEPWALK && algo != FW_NODE2VEC && algo != FW_METAPATH)
+  if (algo != FW_DEEPWALK && algo != FW_NODE2VEC && algo != FW_METAPATH && algo != FW_PPR)
     return fail(FW_EINVAL, "unknown algorithm");
   std::memset(dp, 0, sizeof(*dp));
   uint64_t max_f = 1;
@@ -85,6 +85,12 @@ int check_walk_args(const fw_graph* g, int algo, const fw_params* params, uint64
       return fail(FW_EINVAL, "schema_len must be in 1..16");
     dp->schema_len = params->schema_len;
     std::memcpy(dp->schema, params->schema, sizeof(dp->schema));
+  } else if (algo == FW_PPR) {
+    if (!params) return fail(FW_EINVAL, "PPR needs a stop chance");
+    if (params->stop_den == 0 || params->stop_num > params->stop_den)
+      return fail(FW_EINVAL, "PPR stop chance must satisfy 0 <= stop_num <= stop_den, stop_den > 0");
+    dp->stop_num = params->stop_num;
+    dp->stop_den = params->stop_den;
   }
   const unsigned __int128 bound = (unsigned __int128)g->max_w * max_f * g->max_deg;
   if (bound >> 64) return fail(FW_EOVERFLOW, "max_weight * max_factor * max_degree >= 2^64");

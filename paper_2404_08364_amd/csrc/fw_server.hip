@@ -101,7 +101,7 @@ struct Request {
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
 };
 
-constexpr int kMaxAlgos = 3;
+constexpr int kMaxAlgos = 4;  // DeepWalk, node2vec, MetaPath, PPR
 
 struct Batch {
   std::vector<std::shared_ptr<Request>> reqs;

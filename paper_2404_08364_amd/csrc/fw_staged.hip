@@ -332,7 +332,10 @@ __global__ __launch_bounds__(NW* kWave) void k_walk_persistent(
     for (int s = tid; s < S; s += NT) {
       if (!P.live[s]) continue;
       const uint32_t c = P.cur[s];
-      const uint64_t o = g.off[c], d = g.off[c + 1] - o;
+      const uint64_t o = g.off[c];
+      uint64_t d = g.off[c + 1] - o;
+      // A PPR stop ends the query like a dead end (the tiny stage pads it).
+      if (ALGO == kPPR && ppr_stops(prm, seed, qid_base + P.qid[s], P.t[s])) d = 0;
       P.o[s] = o;
       P.d[s] = d;
       if (d <= cfg.tiny_max)
@@ -489,6 +492,9 @@ hipError_t launch_staged(const LaunchArgs& a, hipStream_t stream) {
     case kMetaPath:
       return wt ? go_nw<kMetaPath, true>(a, a.head, (unsigned)blocks, c.hash_cells, stream)
                 : go_nw<kMetaPath, false>(a, a.head, (unsigned)blocks, c.hash_cells, stream);
+    case kPPR:
+      return wt ? go_nw<kPPR, true>(a, a.head, (unsigned)blocks, c.hash_cells, stream)
+                : go_nw<kPPR, false>(a, a.head, (unsigned)blocks, c.hash_cells, stream);
     default:
       return hipErrorInvalidValue;
   }

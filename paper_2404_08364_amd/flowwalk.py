@@ -16,8 +16,8 @@ _PKG = Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libflowwalk.so"
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EHIP, ECANCELED = 0, -1, -2, -3, -4, -5
-DEEPWALK, NODE2VEC, METAPATH = 0, 1, 2
-ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH}
+DEEPWALK, NODE2VEC, METAPATH, PPR = 0, 1, 2, 3
+ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH, "ppr": PPR}
 MODES = {"auto": 0, "plain": 1, "persistent": 2, "staged": 3}
 END = 0xFFFFFFFF
 
@@ -35,7 +35,8 @@ class Csr(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("f_ret", ctypes.c_uint32), ("f_in", ctypes.c_uint32),
                 ("f_out", ctypes.c_uint32), ("schema_len", ctypes.c_uint32),
-                ("schema", ctypes.c_uint8 * 16)]
+                ("schema", ctypes.c_uint8 * 16),
+                ("stop_num", ctypes.c_uint32), ("stop_den", ctypes.c_uint32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -133,9 +134,11 @@ def node2vec_factors(p_num: int, p_den: int, q_num: int, q_den: int) -> tuple[in
     return out.f_ret, out.f_in, out.f_out
 
 
-def make_params(factors=(1, 1, 1), schema=()) -> Params:
+def make_params(factors=(1, 1, 1), schema=(), stop=(0, 1)) -> Params:
+    """node2vec factors, MetaPath schema, PPR stop chance (num, den)."""
     p = Params()
     p.f_ret, p.f_in, p.f_out = factors
+    p.stop_num, p.stop_den = stop
     p.schema_len = len(schema)
     for i, s in enumerate(schema):
         p.schema[i] = s

@@ -200,6 +200,14 @@ RECIPES = {
         labels=None,
         walk=dict(algo="deepwalk", length=80, seed=42, starts="all"),
     ),
+    # PPR as in the experiments: |V| queries, all from the vertex of largest
+    # degree, stop chance 1/5 per hop; 80 hops cap the (geometric) length.
+    "rmat22_ppr": dict(
+        graph=dict(kind="rmat", scale=22, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=22),
+        weights=dict(kind="zipf", s=1.2, cap=65535, seed=2201),
+        labels=None,
+        walk=dict(algo="ppr", stop=(1, 5), length=80, seed=42, starts="max_degree"),
+    ),
     # Chung-Lu gamma=2.1, 2^24 vertices, ~256M stored edges: MetaPath, unit weights.
     "chunglu24_metapath": dict(
         graph=dict(kind="chung_lu", n=1 << 24, draws=142_000_000, gamma=2.1, i0=4.0, seed=24),
@@ -291,6 +299,9 @@ def recipe_starts(name: str, g: Graph) -> np.ndarray:
     st = RECIPES[name]["walk"]["starts"]
     if st == "all":
         return np.arange(g.n_vertices, dtype=np.uint32)
+    if st == "max_degree":
+        hub = int(np.argmax(g.degrees()))
+        return np.full(g.n_vertices, hub, dtype=np.uint32)
     return uniform_ids(st["n"], g.n_vertices, st["seed"])
 
 

@@ -41,6 +41,9 @@ def _run(recipe, mode, n_strided, n_top, tune=True):
         prm, oprm = fw.make_params(f), oracle.params(*f)
     elif algo == "metapath":
         prm, oprm = fw.make_params(schema=walk["schema"]), oracle.params(schema=walk["schema"])
+    elif algo == "ppr":
+        stop = tuple(walk["stop"])
+        prm, oprm = fw.make_params(stop=stop), oracle.params(stop=stop)
     else:
         prm, oprm = None, oracle.params()
     starts = synth.recipe_starts(recipe, g)
@@ -75,3 +78,11 @@ def test_chunglu24_metapath_full_size():
     [0,1,2,3,4] cycled, all 16,777,216 queries, 20 hops."""
     got = _run("chunglu24_metapath", "persistent", 4000, 300)
     assert (got[:, 1] != 0xFFFFFFFF).any()
+
+
+def test_rmat22_ppr_full_size():
+    """PPR from the vertex of largest degree (163,319 neighbours) for all
+    4,194,304 queries, stop chance 1/5, at most 80 hops."""
+    got = _run("rmat22_ppr", "persistent", 3000, 0)
+    hops = (got[:, 1:] != 0xFFFFFFFF).sum(axis=1)
+    assert (hops == 0).any() and hops.mean() > 2

@@ -24,13 +24,14 @@ def env():
     return torch, fw
 
 
-def _check(env, g, algo, factors, schema, starts, length, seed, mode, qid_base=0, **kw):
+def _check(env, g, algo, factors, schema, starts, length, seed, mode, qid_base=0, stop=(0, 1),
+           **kw):
     torch, fw = env
     G = fw.Graph.of(g)
-    prm = fw.make_params(factors, schema)
+    prm = fw.make_params(factors, schema, stop)
     got = gpu_walk(torch, fw, G, algo, prm, starts, length, seed, mode, qid_base=qid_base, **kw)
-    exp = oracle.walk(g, algo, oracle.params(*factors, schema=schema), starts, length, seed,
-                      qid_base=qid_base)
+    exp = oracle.walk(g, algo, oracle.params(*factors, schema=schema, stop=stop), starts, length,
+                      seed, qid_base=qid_base)
     assert_rows_equal(got, exp, f"{algo} {mode} L={length}")
     return got
 
@@ -82,6 +83,38 @@ def test_powerlaw_graph(env, powerlaw, mode, algo, factors, schema):
     assert g.degrees().max() > 4096
     starts = np.arange(g.n_vertices, dtype=np.uint32)[::5]
     _check(env, g, algo, factors, schema, starts, 12, 31337, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("weighted", [True, False])
+@pytest.mark.parametrize("stop", [(1, 5), (0, 1), (1, 1), (2, 3)])
+@pytest.mark.parametrize("length", [0, 1, 7, 70])
+def test_ppr_tiny6(env, mode, weighted, stop, length):
+    """PPR (stop coin before each hop, DeepWalk weights), including the
+    never-stop and always-stop limits."""
+    g, _ = tiny6(weighted=weighted)
+    starts = np.tile(np.arange(6, dtype=np.uint32), 40)
+    _check(env, g, "ppr", (1, 1, 1), (), starts, length, 2024, mode, qid_base=3, stop=stop)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_ppr_from_the_hub(env, powerlaw, mode):
+    """The experiments' PPR set-up: every query starts at the vertex of
+    largest degree (here about 2,000 neighbours), stop chance 1/5."""
+    g = powerlaw
+    hub = int(np.argmax(g.degrees()))
+    starts = np.full(3000, hub, dtype=np.uint32)
+    got = _check(env, g, "ppr", (1, 1, 1), (), starts, 40, 77, mode, stop=(1, 5))
+    hops = (got[:, 1:] != END).sum(axis=1)
+    assert (hops == 0).any() and hops.max() >= 10
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d", [65, 4097, 70_000])
+def test_ppr_star_hub(env, mode, d):
+    g = _star(d, d + 1)
+    starts = np.zeros(200, np.uint32)
+    _check(env, g, "ppr", (1, 1, 1), (), starts, 5, 4321, mode, stop=(1, 3))
 
 
 @pytest.mark.parametrize("algo,factors,schema", [ALGOS[1], ALGOS[3]])
@@ -146,6 +179,13 @@ def test_errors(env):
     with pytest.raises(fw.FWError) as e:
         fw.walk(B, "node2vec", fw.make_params((0xFFFFFFFF, 1, 1)), ok, 3, 1)
     assert e.value.status == fw.EOVERFLOW
+    for stop in [(1, 0), (5, 4)]:
+        with pytest.raises(fw.FWError) as e:
+            fw.walk(G, "ppr", fw.make_params(stop=stop), ok, 3, 1)
+        assert e.value.status == fw.EINVAL
+    with pytest.raises(fw.FWError) as e:
+        fw.walk(G, "ppr", None, ok, 3, 1)
+    assert e.value.status == fw.EINVAL
     empty = torch.empty(0, dtype=torch.int32, device="cuda")
     out = fw.walk(G, "deepwalk", None, empty, 3, 1)
     assert out.shape == (0, 4)

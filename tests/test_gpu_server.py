@@ -23,14 +23,24 @@ def env():
     return torch, fw, g, fw.Graph.of(g)
 
 
-KINDS = [("deepwalk", (1, 1, 1), ()), ("node2vec", (1, 2, 4), ()), ("metapath", (1, 1, 1), (0, 1, 2))]
+KINDS = [("deepwalk", (1, 1, 1), ()), ("node2vec", (1, 2, 4), ()), ("metapath", (1, 1, 1), (0, 1, 2)),
+         ("ppr", (1, 1, 1), ())]
+STOP = {"ppr": (1, 5)}
+
+
+def _fw_params(fw, algo, f, sch):
+    return fw.make_params(f, sch, STOP.get(algo, (0, 1)))
+
+
+def _oracle_params(algo, f, sch):
+    return oracle.params(*f, schema=sch, stop=STOP.get(algo, (0, 1)))
 
 
 def _requests(g, count, seed):
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(count):
-        algo, f, sch = KINDS[i % 3]
+        algo, f, sch = KINDS[i % len(KINDS)]
         n = int(np.exp(rng.uniform(0, np.log(3000))))
         L = int(rng.integers(10, 81))
         starts = rng.integers(0, g.n_vertices, n).astype(np.uint32)
@@ -49,7 +59,7 @@ def test_mix_equals_alone_and_oracle(env):
         def sub(idx):
             for i in idx:
                 algo, f, sch, st, L, seed = reqs[i]
-                tickets[i] = srv.submit(algo, fw.make_params(f, sch), st, L, seed)
+                tickets[i] = srv.submit(algo, _fw_params(fw, algo, f, sch), st, L, seed)
 
         th = [threading.Thread(target=sub, args=(range(k, len(reqs), 3),)) for k in range(3)]
         for t in th:
@@ -60,10 +70,10 @@ def test_mix_equals_alone_and_oracle(env):
     finally:
         srv.close()
     for (algo, f, sch, st, L, seed), (paths, stats) in zip(reqs, results):
-        exp = oracle.walk(g, algo, oracle.params(*f, schema=sch), st, L, seed)
+        exp = oracle.walk(g, algo, _oracle_params(algo, f, sch), st, L, seed)
         assert_rows_equal(paths, exp, f"served {algo} n={len(st)} L={L}")
         assert stats["status"] == 0 and stats["done_ns"] >= stats["admit_ns"] >= stats["submit_ns"]
-        alone = gpu_walk(torch, fw, G, algo, fw.make_params(f, sch), st, L, seed, "persistent")
+        alone = gpu_walk(torch, fw, G, algo, _fw_params(fw, algo, f, sch), st, L, seed, "persistent")
         assert_rows_equal(paths, alone, "served vs alone")
 
 
@@ -75,10 +85,10 @@ def test_admission_by_memory(env):
     need = max(len(st) * 4 + len(st) * (L + 1) * 4 for (_, _, _, st, L, _) in reqs)
     srv = fw.Server(G, mem_budget_bytes=2 * need + 4096, max_inflight=2)
     try:
-        tickets = [srv.submit(a, fw.make_params(f, s), st, L, sd) for (a, f, s, st, L, sd) in reqs]
+        tickets = [srv.submit(a, _fw_params(fw, a, f, s), st, L, sd) for (a, f, s, st, L, sd) in reqs]
         for (a, f, s, st, L, sd), t in zip(reqs, tickets):
             paths, _ = srv.wait(t)
-            assert_rows_equal(paths, oracle.walk(g, a, oracle.params(*f, schema=s), st, L, sd),
+            assert_rows_equal(paths, oracle.walk(g, a, _oracle_params(a, f, s), st, L, sd),
                               "admission")
         big = np.zeros(1_000_000, dtype=np.uint32)
         with pytest.raises(fw.FWError) as e:
