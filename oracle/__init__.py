@@ -24,6 +24,8 @@ OK, EINVAL, ENOMEM, EOVERFLOW = 0, -1, -2, -3
 DEEPWALK, NODE2VEC, METAPATH, PPR = 0, 1, 2, 3
 ALGOS = {"deepwalk": DEEPWALK, "node2vec": NODE2VEC, "metapath": METAPATH, "ppr": PPR}
 END = 0xFFFFFFFF
+SAMPLERS = {"its": 0, "dprs": 1, "zprs": 2}
+ZPRS_LANES = 64
 
 
 class Params(ctypes.Structure):
@@ -71,6 +73,14 @@ def bind(lib):
     lib.fwo_stop_coin.restype = i32
     lib.fwo_stop.argtypes = [u64, u64, u64, u32, u32]
     lib.fwo_stop.restype = i32
+    lib.fwo_entry_draw.argtypes = [u64, u64, u64, u64]
+    lib.fwo_entry_draw.restype = u64
+    lib.fwo_zigzag_order.argtypes = [u64, u32, vp]
+    lib.fwo_zigzag_order.restype = None
+    lib.fwo_reservoir.argtypes = [vp, vp, vp, u64]
+    lib.fwo_reservoir.restype = ctypes.c_int64
+    lib.fwo_walk_sampler.argtypes = [pg, i32, pp, i32, vp, u64, u32, u64, u64, vp]
+    lib.fwo_walk_sampler.restype = i32
     lib.fwo_scale.argtypes = [u64, u64]
     lib.fwo_scale.restype = u64
     lib.fwo_pick.argtypes = [vp, u64, u64]
@@ -188,22 +198,44 @@ def transition_weights(g, algo, prm: Params | None, prev: int, cur: int, t: int)
     return out[:d]
 
 
-def walk_status(g, algo, prm, starts, length: int, seed: int, qid_base: int = 0):
+def walk_status(g, algo, prm, starts, length: int, seed: int, qid_base: int = 0,
+                sampler="its"):
     """Returns (status, paths); paths is uint32[n, length+1]."""
     hg = HostGraph.of(g)
     st = np.ascontiguousarray(starts, dtype=np.uint32)
     out = np.zeros((st.shape[0], length + 1), dtype=np.uint32)
     a = ALGOS.get(algo, algo)
-    rc = _load().fwo_walk(ctypes.byref(hg.c), a, None if prm is None else ctypes.byref(prm),
-                          st.ctypes.data, st.shape[0], length, seed, qid_base, out.ctypes.data)
+    smp = SAMPLERS.get(sampler, sampler)
+    rc = _load().fwo_walk_sampler(ctypes.byref(hg.c), a,
+                                  None if prm is None else ctypes.byref(prm), smp,
+                                  st.ctypes.data, st.shape[0], length, seed, qid_base,
+                                  out.ctypes.data)
     return int(rc), out
 
 
-def walk(g, algo, prm, starts, length: int, seed: int, qid_base: int = 0) -> np.ndarray:
-    rc, out = walk_status(g, algo, prm, starts, length, seed, qid_base)
+def walk(g, algo, prm, starts, length: int, seed: int, qid_base: int = 0,
+         sampler="its") -> np.ndarray:
+    rc, out = walk_status(g, algo, prm, starts, length, seed, qid_base, sampler)
     if rc:
         raise OracleError(rc, "fwo_walk")
     return out
+
+
+def entry_draw(seed: int, qid: int, t: int, i: int) -> int:
+    return int(_load().fwo_entry_draw(seed, qid, t, i))
+
+
+def zigzag_order(d: int, k: int = ZPRS_LANES) -> np.ndarray:
+    out = np.zeros(max(d, 1), dtype=np.uint64)
+    _load().fwo_zigzag_order(d, k, out.ctypes.data)
+    return out[:d]
+
+
+def reservoir(w, u, order) -> int:
+    w = np.ascontiguousarray(w, dtype=np.uint64)
+    u = np.ascontiguousarray(u, dtype=np.uint64)
+    o = np.ascontiguousarray(order, dtype=np.uint64)
+    return int(_load().fwo_reservoir(w.ctypes.data, u.ctypes.data, o.ctypes.data, w.shape[0]))
 
 
 def walk_ids(g, algo, prm, starts, qids, length: int, seed: int) -> np.ndarray:

@@ -69,6 +69,34 @@ int fwo_stop(uint64_t seed, uint64_t qid, uint64_t t, uint32_t stop_num, uint32_
   return fwo_stop_coin(out[1], stop_num, stop_den);
 }
 
+uint64_t fwo_entry_draw(uint64_t seed, uint64_t qid, uint64_t t, uint64_t i) {
+  uint64_t ctr[4] = {qid, t, i / 4, 1};
+  uint64_t key[2] = {seed, 0};
+  uint64_t out[4];
+  fwo_philox4x64_10(ctr, key, out);
+  return out[i % 4];
+}
+
+void fwo_zigzag_order(uint64_t d, uint32_t k, uint64_t* order) {
+  uint64_t quads = (d + 3) / 4, m = 0;
+  for (uint32_t j = 0; j < k; ++j)
+    for (uint64_t q = j; q < quads; q += k)
+      for (uint64_t i = 4 * q; i < 4 * q + 4 && i < d; ++i) order[m++] = i;
+}
+
+int64_t fwo_reservoir(const uint64_t* w, const uint64_t* u, const uint64_t* order, uint64_t d) {
+  int64_t selected = -1;
+  uint64_t total = 0;
+  for (uint64_t m = 0; m < d; ++m) {
+    uint64_t i = order[m];
+    if (w[i] == 0) continue;
+    total += w[i];
+    unsigned __int128 p = (unsigned __int128)u[i] * total;
+    if ((uint64_t)(p >> 64) < w[i]) selected = (int64_t)i;
+  }
+  return selected;
+}
+
 uint64_t fwo_scale(uint64_t u, uint64_t total) {
   unsigned __int128 p = (unsigned __int128)u * total;
   return (uint64_t)(p >> 64);
@@ -222,11 +250,31 @@ static uint64_t max_degree(const fwo_graph* g) {
   return m;
 }
 
-/* One query: Algorithm 1's loop with inverse transform sampling.  A PPR
- * query first tosses its stop coin at every hop; `length` caps its hops. */
-static int walk_one(const fwo_graph* g, int algo, const fwo_params* p, uint32_t start,
-                    uint64_t qid, uint32_t length, uint64_t seed, uint64_t* wbuf,
-                    uint32_t* row) {
+/* Scratch of one walker: weights, entry words and a visiting order, each
+ * max_degree long. */
+typedef struct {
+  uint64_t *w, *u, *order;
+} scratch;
+
+/* The pick of one hop among d entries of weights w (total > 0). */
+static int64_t pick_entry(int sampler, const scratch* b, uint64_t d, uint64_t total,
+                          uint64_t seed, uint64_t qid, uint32_t t) {
+  if (sampler == FWO_SAMPLER_ITS) return fwo_pick(b->w, d, fwo_scale(fwo_draw(seed, qid, t), total));
+  for (uint64_t i = 0; i < d; ++i) b->u[i] = fwo_entry_draw(seed, qid, t, i);
+  if (sampler == FWO_SAMPLER_DPRS)
+    for (uint64_t i = 0; i < d; ++i) b->order[i] = i;
+  else
+    fwo_zigzag_order(d, FWO_ZPRS_LANES, b->order);
+  return fwo_reservoir(b->w, b->u, b->order, d);
+}
+
+/* One query: Algorithm 1's loop with inverse transform sampling (or a
+ * reservoir sampler).  A PPR query first tosses its stop coin at every hop;
+ * `length` caps its hops. */
+static int walk_one(const fwo_graph* g, int algo, const fwo_params* p, int sampler,
+                    uint32_t start, uint64_t qid, uint32_t length, uint64_t seed,
+                    const scratch* scr, uint32_t* row) {
+  uint64_t* wbuf = scr->w;
   if (start >= g->n_vertices) return FWO_EINVAL;
   row[0] = start;
   for (uint32_t t = 0; t < length; ++t) {
@@ -245,37 +293,61 @@ static int walk_one(const fwo_graph* g, int algo, const fwo_params* p, uint32_t 
       for (uint32_t s = t + 1; s <= length; ++s) row[s] = FWO_END;
       return FWO_OK;
     }
-    uint64_t r = fwo_scale(fwo_draw(seed, qid, t), total);
-    int64_t i = fwo_pick(wbuf, d, r);
+    int64_t i = pick_entry(sampler, scr, d, total, seed, qid, t);
     row[t + 1] = g->adj[b + (uint64_t)i];
   }
   return FWO_OK;
 }
 
-static int walk_setup(const fwo_graph* g, int algo, const fwo_params* p, uint64_t** wbuf) {
+static void scratch_free(scratch* b) {
+  free(b->w);
+  free(b->u);
+  free(b->order);
+}
+
+static int walk_setup(const fwo_graph* g, int algo, const fwo_params* p, int sampler,
+                      scratch* b) {
+  b->w = b->u = b->order = NULL;
   if (!g || !g->offsets) return FWO_EINVAL;
+  if (sampler < FWO_SAMPLER_ITS || sampler > FWO_SAMPLER_ZPRS) return FWO_EINVAL;
   int rc = check_params(g, algo, p);
   if (rc) return rc;
   rc = check_overflow(g, algo, p);
   if (rc) return rc;
   uint64_t md = max_degree(g);
-  *wbuf = (uint64_t*)malloc((md ? md : 1) * sizeof(uint64_t));
-  return *wbuf ? FWO_OK : FWO_ENOMEM;
+  size_t bytes = (md ? md : 1) * sizeof(uint64_t);
+  b->w = (uint64_t*)malloc(bytes);
+  if (sampler != FWO_SAMPLER_ITS) {
+    b->u = (uint64_t*)malloc(bytes);
+    b->order = (uint64_t*)malloc(bytes);
+  }
+  if (!b->w || (sampler != FWO_SAMPLER_ITS && (!b->u || !b->order))) {
+    scratch_free(b);
+    return FWO_ENOMEM;
+  }
+  return FWO_OK;
+}
+
+int fwo_walk_sampler(const fwo_graph* g, int algo, const fwo_params* p, int sampler,
+                     const uint32_t* starts, uint64_t n, uint32_t length, uint64_t seed,
+                     uint64_t qid_base, uint32_t* out_paths) {
+  if (n == 0) return FWO_OK;
+  if (!starts || !out_paths) return FWO_EINVAL;
+  scratch b;
+  int rc = walk_setup(g, algo, p, sampler, &b);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < n && rc == FWO_OK; ++i)
+    rc = walk_one(g, algo, p, sampler, starts[i], qid_base + i, length, seed, &b,
+                  out_paths + i * ((uint64_t)length + 1));
+  scratch_free(&b);
+  return rc;
 }
 
 int fwo_walk(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
              uint64_t n, uint32_t length, uint64_t seed, uint64_t qid_base,
              uint32_t* out_paths) {
-  if (n == 0) return FWO_OK;
-  if (!starts || !out_paths) return FWO_EINVAL;
-  uint64_t* wbuf = NULL;
-  int rc = walk_setup(g, algo, p, &wbuf);
-  if (rc) return rc;
-  for (uint64_t i = 0; i < n && rc == FWO_OK; ++i)
-    rc = walk_one(g, algo, p, starts[i], qid_base + i, length, seed, wbuf,
-                  out_paths + i * ((uint64_t)length + 1));
-  free(wbuf);
-  return rc;
+  return fwo_walk_sampler(g, algo, p, FWO_SAMPLER_ITS, starts, n, length, seed, qid_base,
+                          out_paths);
 }
 
 int fwo_walk_ids(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
@@ -283,12 +355,12 @@ int fwo_walk_ids(const fwo_graph* g, int algo, const fwo_params* p, const uint32
                  uint32_t* out_paths) {
   if (m == 0) return FWO_OK;
   if (!starts || !qids || !out_paths) return FWO_EINVAL;
-  uint64_t* wbuf = NULL;
-  int rc = walk_setup(g, algo, p, &wbuf);
+  scratch b;
+  int rc = walk_setup(g, algo, p, FWO_SAMPLER_ITS, &b);
   if (rc) return rc;
   for (uint64_t j = 0; j < m && rc == FWO_OK; ++j)
-    rc = walk_one(g, algo, p, starts[qids[j]], qids[j], length, seed, wbuf,
+    rc = walk_one(g, algo, p, FWO_SAMPLER_ITS, starts[qids[j]], qids[j], length, seed, &b,
                   out_paths + j * ((uint64_t)length + 1));
-  free(wbuf);
+  scratch_free(&b);
   return rc;
 }

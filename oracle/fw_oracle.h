@@ -101,11 +101,43 @@ int fwo_validate(const fwo_graph* g);
 int fwo_transition_weights(const fwo_graph* g, int algo, const fwo_params* p, uint32_t prev,
                            uint32_t cur, uint32_t t, uint64_t* w_out);
 
+/* Reservoir samplers (section 4).  DPRS (Algorithm 3) visits the neighbour
+ * sequence S in order; ZPRS (Algorithm 4) visits it in the zig-zag order S'
+ * of k lanes: the d entries form quads of four consecutive entries (entry i
+ * is in quad i / 4), lane j owns quads j, j + k, j + 2k, ... and visits
+ * their entries in order, and S' is lane 0's entries, then lane 1's, ...
+ * Each visited entry i of weight w_i replaces the selection when
+ * floor(u_i * W / 2^64) < w_i, with W the total of the entries visited so
+ * far including i (the integer form of "random(0,1) < w_i / W"); the result
+ * is the last selection.  Either way neighbour i is picked with chance
+ * w_i / T (Propositions 1 and 2), but which neighbour is picked differs. */
+#define FWO_SAMPLER_ITS 0
+#define FWO_SAMPLER_DPRS 1
+#define FWO_SAMPLER_ZPRS 2
+#define FWO_ZPRS_LANES 64
+
+/* The uniform word of entry i at hop t: word (i mod 4) of
+ * Philox4x64-10(counter = (qid, t, floor(i / 4), 1), key = (seed, 0)). */
+uint64_t fwo_entry_draw(uint64_t seed, uint64_t qid, uint64_t t, uint64_t i);
+
+/* ZPRS's visiting order of d entries with k lanes into order[0 .. d). */
+void fwo_zigzag_order(uint64_t d, uint32_t k, uint64_t* order);
+
+/* Sequential weighted reservoir sampling (Algorithm 2) over the entries
+ * order[0 .. d) with weights w[] and words u[] (indexed by entry); returns
+ * the last selected entry, or -1 when every weight is 0. */
+int64_t fwo_reservoir(const uint64_t* w, const uint64_t* u, const uint64_t* order, uint64_t d);
+
 /* Walks n queries.  Query i has id qid_base + i and starts at starts[i];
  * row i of out_paths (length + 1 entries) receives its path. */
 int fwo_walk(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,
              uint64_t n, uint32_t length, uint64_t seed, uint64_t qid_base,
              uint32_t* out_paths);
+
+/* fwo_walk with the pick of each hop made by `sampler` (FWO_SAMPLER_*). */
+int fwo_walk_sampler(const fwo_graph* g, int algo, const fwo_params* p, int sampler,
+                     const uint32_t* starts, uint64_t n, uint32_t length, uint64_t seed,
+                     uint64_t qid_base, uint32_t* out_paths);
 
 /* Walks the m queries qids[j] (start starts[qids[j]]), row j of out_paths. */
 int fwo_walk_ids(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,

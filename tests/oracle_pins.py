@@ -404,8 +404,128 @@ def pin_ppr_limits():
         assert rc == oracle.EINVAL, stop
 
 
+def pin_entry_draw_keying(cases=100):
+    """A reservoir sampler's word for entry i at hop t is word i mod 4 of the
+    block at counter (qid, t, i div 4, 1), key (seed, 0) (numpy's Philox)."""
+    rng = np.random.default_rng(17)
+    for _ in range(cases):
+        seed, qid, t, i = (int(x) for x in rng.integers(0, 1 << 40, 4))
+        t %= 1000
+        i %= 100_000
+        block = _numpy_philox_block([qid, t, i // 4, 1], [seed, 0])
+        assert oracle.entry_draw(seed, qid, t, i) == block[i % 4], (seed, qid, t, i)
+
+
+def pin_zigzag_golden():
+    import json
+    from pathlib import Path
+    cases = json.loads((Path(__file__).parent / "golden" / "zigzag_order.json").read_text())
+    for c in cases["cases"]:
+        assert oracle.zigzag_order(c["d"], c["k"]).tolist() == c["order"], c
+
+
+def pin_reservoir_extremes():
+    """Words 0 select every entry, so the last positive weight wins; words
+    2^64 - 1 select only the first positive weight (floor((2^64-1) W / 2^64)
+    = W - 1 < w only while W = w); no positive weight selects nothing."""
+    rng = np.random.default_rng(19)
+    for _ in range(200):
+        d = int(rng.integers(1, 40))
+        w = rng.integers(0, 4, d).astype(np.uint64)
+        order = rng.permutation(d).astype(np.uint64)
+        pos = [int(i) for i in order if w[int(i)] > 0]
+        got0 = oracle.reservoir(w, np.zeros(d, np.uint64), order)
+        gotm = oracle.reservoir(w, np.full(d, M64, np.uint64), order)
+        assert got0 == (pos[-1] if pos else -1)
+        assert gotm == (pos[0] if pos else -1)
+
+
+def pin_reservoir_distribution(n=200_000):
+    """Algorithm 2 picks entry i with chance w_i / T in any visiting order
+    (Proposition 1), here with words from numpy's default generator."""
+    from scipy.stats import chisquare
+    w = np.array([3, 0, 5, 1, 7, 2, 0, 4], dtype=np.uint64)
+    rng = np.random.default_rng(23)
+    for order in [np.arange(8), np.array([5, 2, 7, 0, 4, 1, 6, 3])]:
+        counts = np.zeros(8, dtype=np.int64)
+        for _ in range(n):
+            u = rng.integers(0, 1 << 63, 8, dtype=np.uint64) * np.uint64(2) + \
+                rng.integers(0, 2, 8, dtype=np.uint64)
+            counts[oracle.reservoir(w, u, order.astype(np.uint64))] += 1
+        nz = w > 0
+        assert counts[~nz].sum() == 0
+        exp = w[nz].astype(np.float64) / float(w.sum()) * n
+        assert chisquare(counts[nz], exp).pvalue > 1e-4, (order, counts)
+
+
+def _hub_graph(d=700):
+    """Vertex 0 joined to 1..d (varied weights), plus a ring over the leaves
+    so that walks continue."""
+    edges = [(0, i, 1 + (i * 37) % 50, 0) for i in range(1, d + 1)]
+    edges += [(i, i % d + 1, 1 + i % 3, 0) for i in range(1, d + 1)]
+    return csr_from_edges(d + 1, edges)
+
+
+def _python_reservoir_walk(g, start, qid, length, seed, sampler, k=64):
+    """Rebuilt from independent parts: numpy's Philox words, Python integers,
+    the visiting order as a sort by (lane, quad, position)."""
+    row = [start]
+    for t in range(length):
+        cur = row[-1]
+        b, e = int(g.offsets[cur]), int(g.offsets[cur + 1])
+        d = e - b
+        w = [int(g.weights[b + i]) for i in range(d)]
+        if sum(w) == 0:
+            return row + [END] * (length - t)
+        if sampler == "dprs":
+            order = list(range(d))
+        else:
+            order = sorted(range(d), key=lambda i: ((i // 4) % k, i // 4, i % 4))
+        sel, tot = -1, 0
+        for i in order:
+            if w[i] == 0:
+                continue
+            tot += w[i]
+            u = _numpy_philox_block([qid, t, i // 4, 1], [seed, 0])[i % 4]
+            if (u * tot) >> 64 < w[i]:
+                sel = i
+        row.append(int(g.adj[b + sel]))
+    return row
+
+
+def pin_reservoir_walks_rebuilt():
+    g = _hub_graph()
+    starts = np.array([0, 0, 0, 5, 0, 17, 0, 0], dtype=np.uint32)
+    for sampler in ["dprs", "zprs"]:
+        rows = oracle.walk(g, "deepwalk", oracle.params(), starts, 3, 55, qid_base=9,
+                           sampler=sampler)
+        for i, s in enumerate(starts):
+            exp = _python_reservoir_walk(g, int(s), 9 + i, 3, 55, sampler)
+            assert rows[i].tolist() == exp, (sampler, i, rows[i], exp)
+
+
+def pin_reservoir_hop_distribution(n=300_000):
+    """One hop from a 700-neighbour hub: both samplers pick neighbour i with
+    chance w_i / T (chi-square), while ZPRS's picks differ from DPRS's."""
+    from scipy.stats import chisquare
+    g = _hub_graph()
+    b, e = int(g.offsets[0]), int(g.offsets[1])
+    w = g.weights[b:e].astype(np.float64)
+    starts = np.zeros(n, dtype=np.uint32)
+    got = {}
+    for sampler in ["dprs", "zprs"]:
+        rows = oracle.walk(g, "deepwalk", oracle.params(), starts, 1, 8, sampler=sampler)
+        counts = np.bincount(rows[:, 1].astype(np.int64) - 1, minlength=e - b)
+        assert chisquare(counts, w / w.sum() * n).pvalue > 1e-4, sampler
+        got[sampler] = rows[:, 1]
+    assert (got["dprs"] != got["zprs"]).mean() > 0.5
+
+
 ALL_PINS = [pin_philox_kat, pin_philox_numpy, pin_draw_keying, pin_scale_closed_form,
             pin_pick_bruteforce, pin_hand_weights, pin_walk_rebuilt, pin_chi2_paths, pin_identities,
             pin_regular_uniform, pin_path_graph_edges, pin_errors,
             pin_zero_length_and_dead_ends, pin_stop_coin_closed_form, pin_stop_keying,
-            pin_ppr_rebuilt, pin_ppr_length_distribution, pin_ppr_limits]
+            pin_ppr_rebuilt, pin_ppr_length_distribution, pin_ppr_limits,
+            pin_entry_draw_keying, pin_zigzag_golden, pin_reservoir_extremes,
+            pin_reservoir_distribution, pin_reservoir_walks_rebuilt,
+            pin_reservoir_hop_distribution]

@@ -28,6 +28,15 @@ MUTANTS = {
     "ppr_coin_le": ("(uint64_t)(p >> 64) < stop_num;", "(uint64_t)(p >> 64) <= stop_num;"),
     "ppr_coin_hop": ("fwo_stop(seed, qid, t, p->stop_num", "fwo_stop(seed, qid, t + 1, p->stop_num"),
     "ppr_first_coin": ("if (algo == FWO_PPR && fwo_stop(", "if (algo == FWO_PPR && t > 0 && fwo_stop("),
+    "entry_word": ("return out[i % 4];", "return out[(i + 1) % 4];"),
+    "entry_counter": ("uint64_t ctr[4] = {qid, t, i / 4, 1};", "uint64_t ctr[4] = {qid, t, i / 4, 0};"),
+    "zigzag_partial_quad": ("uint64_t quads = (d + 3) / 4, m = 0;", "uint64_t quads = d / 4, m = 0;"),
+    "reservoir_le": ("if ((uint64_t)(p >> 64) < w[i]) selected", "if ((uint64_t)(p >> 64) <= w[i]) selected"),
+    "reservoir_exclusive_total": (
+        "    total += w[i];\n    unsigned __int128 p = (unsigned __int128)u[i] * total;\n"
+        "    if ((uint64_t)(p >> 64) < w[i]) selected = (int64_t)i;",
+        "    unsigned __int128 p = (unsigned __int128)u[i] * total;\n"
+        "    if ((uint64_t)(p >> 64) < w[i]) selected = (int64_t)i;\n    total += w[i];"),
     "padding": ("for (uint32_t s = t + 1; s <= length; ++s)", "for (uint32_t s = t + 1; s < length; ++s)"),
 }
 
