@@ -167,6 +167,22 @@ typedef struct fw_tune {
   uint32_t hash_cells;   /* LDS cells for the node2vec membership structure */
 } fw_tune;
 
+/* How each hop picks its neighbour (fw_walk_opts.sampler).
+ *   FW_SAMPLER_ITS   the exact inverse-CDF pick above (every mode).
+ *   FW_SAMPLER_DPRS  direct parallel reservoir sampling (Algorithm 3);
+ *   FW_SAMPLER_ZPRS  zig-zag parallel reservoir sampling (Algorithm 4).
+ * The reservoir samplers draw one word per entry i of the neighbour
+ * sequence, word i mod 4 of Philox4x64-10(counter = (qid, t, i / 4, 1),
+ * key = (seed, 0)), and visiting entry i with running total W (including
+ * it) select it when floor(u_i * W / 2^64) < w'_i; the last selection is
+ * the pick.  DPRS visits the entries in CSR order.  ZPRS visits them in the
+ * zig-zag order of 64 lanes over quads: lane j owns quads j, j + 64, ...
+ * (quad q = entries 4q .. 4q + 3), lane 0's entries first.  Both pick
+ * neighbour i with chance w'_i / T (Propositions 1 and 2), but not the same
+ * neighbour as ITS or as each other.  They run in FW_MODE_PLAIN only; node2vec
+ * membership is a binary search of N(prev) per entry, as in the paper. */
+typedef enum { FW_SAMPLER_ITS = 0, FW_SAMPLER_DPRS = 1, FW_SAMPLER_ZPRS = 2 } fw_sampler;
+
 typedef struct fw_walk_opts {
   int mode;               /* fw_mode */
   void* stream;           /* hipStream_t to run on (NULL = null stream) */
@@ -176,6 +192,7 @@ typedef struct fw_walk_opts {
   const fw_tune* tune;    /* NULL = tuned/default configuration */
   int use_graph;          /* 1: replay a captured hipGraph of the launch
                              (persistent form; ignored otherwise) */
+  int sampler;            /* fw_sampler (0 = FW_SAMPLER_ITS) */
 } fw_walk_opts;
 
 /* fw_walk with options (opts may be NULL: synchronous FW_MODE_AUTO on the

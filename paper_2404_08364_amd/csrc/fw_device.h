@@ -29,15 +29,17 @@ struct DevParams {
 };
 
 // ---------------------------------------------------------------------------
-// Step draw: word 0 of Philox4x64-10 (Salmon et al., SC 2011) at counter
-// (qid, t, 0, 0), key (seed, 0).  One draw per hop, no generator state.
-// Word 1 of the same block is PPR's stop coin.
+// Philox4x64-10 (Salmon et al., SC 2011): the four words of the block at
+// counter (c0, c1, c2, c3), key (seed, 0).  The step draw is word 0 of the
+// block at (qid, t, 0, 0), one per hop, no generator state; word 1 of the
+// same block is PPR's stop coin; the reservoir samplers draw entry i's word
+// from the block at (qid, t, i / 4, 1).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t philox_draw2(uint64_t seed, uint64_t qid, uint64_t t,
-                                                 uint64_t& word1) {
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t seed, uint64_t out[4]) {
   constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
   constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
-  uint64_t c0 = qid, c1 = t, c2 = 0, c3 = 0, k0 = seed, k1 = 0;
+  uint64_t k0 = seed, k1 = 0;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t h0 = __umul64hi(kM0, c0), l0 = kM0 * c0;
@@ -49,8 +51,18 @@ __device__ __forceinline__ uint64_t philox_draw2(uint64_t seed, uint64_t qid, ui
     k0 += kW0;
     k1 += kW1;
   }
-  word1 = c1;
-  return c0;
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+__device__ __forceinline__ uint64_t philox_draw2(uint64_t seed, uint64_t qid, uint64_t t,
+                                                 uint64_t& word1) {
+  uint64_t w[4];
+  philox4x64_10(qid, t, 0, 0, seed, w);
+  word1 = w[1];
+  return w[0];
 }
 
 __device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint64_t qid, uint64_t t) {

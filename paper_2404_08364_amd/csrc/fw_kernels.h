@@ -55,6 +55,8 @@ struct ReqTable {
 };
 
 hipError_t launch_plain(const LaunchArgs& a, hipStream_t stream);
+// Reservoir-sampling walkers: sampler 1 = DPRS, 2 = ZPRS (plain assignment).
+hipError_t launch_reservoir(const LaunchArgs& a, int sampler, hipStream_t stream);
 // Multi-request persistent launch on `stream` (resets `head` first).
 hipError_t launch_persistent_multi(int algo, const DevGraph& g, const ReqTable& t,
                                    uint32_t* status, uint64_t* head, int num_cus,

@@ -321,8 +321,12 @@ struct Reqs {
   __device__ __forceinline__ ReqDesc get(uint32_t r) const { return MULTI ? tab.reqs[r] : one; }
 };
 
+// Eight wavefronts per SIMD (64 VGPRs): the walk is bound by the latency of
+// dependent loads (offsets, then the slice, then the LDS membership probes),
+// so occupancy pays more than the few per-hop register spills it costs.
 template <int ALGO, bool WEIGHTED, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_walk_persistent(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+k_walk_persistent(
     DevGraph g, Reqs<MULTI> rq, uint32_t* __restrict__ status, uint64_t* __restrict__ head,
     TuneCfg cfg) {
   const int lane = lane_id();

@@ -50,7 +50,7 @@ TuneCfg default_tune(const fw_graph* g, int algo, bool staged) {
     c.slots = 4;
     c.tiny_max = 16;
     c.hub_min = 17;
-    c.wgs_per_cu = 4;
+    c.wgs_per_cu = 8;  // the kernel is built for 8 wavefronts per SIMD
     c.hash_cells = (algo == 1) ? 1024 : 64;
   }
   return c;
@@ -184,7 +184,7 @@ int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts,
   // Coordinate search: occupancy x membership-table size, then the tiny
   // threshold.  Configurations that do not fit the LDS are skipped.
   const uint32_t cells[] = {256, 512, 1024, 2048, 4096};
-  const uint32_t wgs[] = {2, 3, 4, 5, 6, 8};
+  const uint32_t wgs[] = {3, 4, 5, 6, 7, 8};
   for (uint32_t hc : cells) {
     if (algo != 1 && hc != 256) continue;  // only node2vec uses the tables
     for (uint32_t w : wgs) {

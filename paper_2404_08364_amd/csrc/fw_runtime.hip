@@ -297,7 +297,13 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
   a.head = g->d_head + fw::kHeadStride * (g->launches.fetch_add(1) % fw::kHeadSlots);
   a.num_cus = g->num_cus;
   hipError_t e;
-  if (o.mode == FW_MODE_PLAIN) {
+  if (o.sampler != FW_SAMPLER_ITS) {
+    if (o.sampler != FW_SAMPLER_DPRS && o.sampler != FW_SAMPLER_ZPRS)
+      return fail(FW_EINVAL, "unknown sampler");
+    if (o.mode != FW_MODE_PLAIN)
+      return fail(FW_EINVAL, "the reservoir samplers run in FW_MODE_PLAIN");
+    e = fw::launch_reservoir(a, o.sampler, stream);
+  } else if (o.mode == FW_MODE_PLAIN) {
     e = fw::launch_plain(a, stream);
   } else if (o.mode == FW_MODE_PERSISTENT || o.mode == FW_MODE_AUTO ||
              o.mode == FW_MODE_STAGED) {

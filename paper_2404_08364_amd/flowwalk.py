@@ -56,7 +56,10 @@ class Tune(ctypes.Structure):
 class WalkOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("stream", ctypes.c_void_p), ("async_", ctypes.c_int),
                 ("qid_base", ctypes.c_uint64), ("tune", ctypes.POINTER(Tune)),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("sampler", ctypes.c_int)]
+
+
+SAMPLERS = {"its": 0, "dprs": 1, "zprs": 2}
 
 
 class ServerOpts(ctypes.Structure):
@@ -210,9 +213,10 @@ def _stream_handle(stream):
 
 def walk_ptr(graph: Graph, algo, prm: Params | None, starts_ptr: int, n: int, length: int,
              seed: int, out_ptr: int, mode="auto", stream=None, async_=False, qid_base=0,
-             tune: Tune | None = None, use_graph=False) -> int:
+             tune: Tune | None = None, use_graph=False, sampler="its") -> int:
     """Raw-pointer form of fw_walk_ex; returns the status."""
     o = WalkOpts()
+    o.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.stream = _stream_handle(stream)
     o.async_ = int(bool(async_))
@@ -226,9 +230,10 @@ def walk_ptr(graph: Graph, algo, prm: Params | None, starts_ptr: int, n: int, le
 
 def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int, out=None,
          mode="auto", stream=None, async_=False, qid_base=0, tune: Tune | None = None,
-         use_graph=False):
+         use_graph=False, sampler="its"):
     """Runs len(starts) queries; returns the int32 tensor [n, length + 1]
-    (FW_END reads as -1)."""
+    (FW_END reads as -1).  sampler: "its" (any mode), "dprs" or "zprs"
+    (mode "plain")."""
     import torch
     if starts.device.type != "cuda":
         raise ValueError("starts must be a device tensor")
@@ -244,7 +249,7 @@ def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
     if stream is None:
         stream = torch.cuda.current_stream(starts.device)
     rc = walk_ptr(graph, algo, prm, starts.data_ptr(), n, length, seed, out.data_ptr(), mode,
-                  stream, async_, qid_base, tune, use_graph)
+                  stream, async_, qid_base, tune, use_graph, sampler)
     _check(rc, "fw_walk_ex")
     return out
 
