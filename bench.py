@@ -262,6 +262,44 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
                 sweep=out)
 
 
+def sampler_sweep():
+    """One hop from the hub of a star graph (d leaves, weights U[1,255]) for
+    every query, in the plain walker (one wavefront per query), with each
+    sampler: the per-hop cost of ITS (two passes, one draw), DPRS (one pass,
+    a scan and a ballot per 256 entries, one word per entry) and ZPRS (two
+    passes, one scan, one word per entry) as the degree grows."""
+    import torch
+    from paper_2404_08364_amd import flowwalk as fw
+    rng = np.random.default_rng(99)
+    rows = []
+    for k in range(2, 21):
+        d = 1 << k
+        off = np.concatenate([[0], d + np.arange(d + 1, dtype=np.uint64)]).astype(np.uint64)
+        adj = np.concatenate([np.arange(1, d + 1), np.zeros(d)]).astype(np.uint32)
+        w = rng.integers(1, 256, 2 * d).astype(np.uint32)
+        G = fw.Graph.upload(off, adj, w, None)
+        n = int(min(1 << 20, max(16384, (1 << 30) // d)))
+        st = torch.zeros(n, dtype=torch.int32, device="cuda")
+        out = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        res = dict(degree=d, queries=n)
+        for smp in ["its", "dprs", "zprs"]:
+            ms = []
+            for rep in range(4):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fw.walk(G, "deepwalk", None, st, 1, 7 + rep, out=out, mode="plain", sampler=smp)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep:
+                    ms.append(e0.elapsed_time(e1))
+            t = float(np.median(ms))
+            res[smp] = dict(ms=t, ns_per_hop=t * 1e6 / n, gelem_per_s=n * d / (t / 1e3) / 1e9)
+        G.free()
+        rows.append(res)
+        print(json.dumps(res), flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +320,8 @@ def main():
     ap.add_argument("--serve-workload", default="rmat24_serve")
     ap.add_argument("--queries", type=int, default=0,
                     help="time only the first N queries of the workload (0 = all)")
+    ap.add_argument("--sampler-sweep", action="store_true",
+                    help="only time ITS / DPRS / ZPRS hops by degree on star graphs")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
     args = ap.parse_args()
@@ -298,6 +338,10 @@ def main():
         dt = time.perf_counter() - t0
         print(json.dumps({"calibrate_copy_bytes": n * 4, "seconds": dt,
                           "gbps": 2 * n * 4 / dt / 1e9}), flush=True)
+        return
+
+    if args.sampler_sweep:
+        sampler_sweep()
         return
 
     if args.gpus != 1:
