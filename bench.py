@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--serve-workload", default="rmat24_serve")
     ap.add_argument("--queries", type=int, default=0,
                     help="time only the first N queries of the workload (0 = all)")
+    ap.add_argument("--host-batches", type=int, default=0,
+                    help="also time fw_walk_host (rows to host memory) in this many batches")
     ap.add_argument("--sampler-sweep", action="store_true",
                     help="only time ITS / DPRS / ZPRS hops by degree on star graphs")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -423,6 +425,22 @@ def main():
         plain = dict(ms_per_step=ms_p, value=hops / (ms_p / 1e3), identical_paths=same)
         log(f"plain: {ms_p:.1f} ms/step, identical={same}")
 
+    host = None
+    if args.host_batches:
+        L1 = L + 1
+        budget = -(-n // args.host_batches) * 2 * (L + 2) * 4
+        fw.walk_host(G, algo, prm, starts_np[: min(n, 65536)], L, seed)  # warm
+        t_h = time.perf_counter()
+        rows_h, B, nb = fw.walk_host(G, algo, prm, starts_np, L, seed, device_budget_bytes=budget)
+        dt_h = time.perf_counter() - t_h
+        same_h = bool(np.array_equal(rows_h, paths_main.cpu().numpy().view(np.uint32)))
+        host = dict(ms=dt_h * 1e3, value=hops / dt_h, batch_queries=B, batches=nb,
+                    result_bytes=n * L1 * 4, identical_paths=same_h,
+                    note="rows to pageable host memory through two pinned staging buffers "
+                         "(PCIe-inclusive); not the headline value")
+        del rows_h
+        log(f"host batches: {host}")
+
     copy_gbps = copy_bandwidth(torch, dev)
     log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
 
@@ -483,6 +501,7 @@ def main():
         "traffic_gbps": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
         "device": device_facts(torch, dev),
         "plain": plain,
+        "host_batches": host,
         "cpu_baseline": cpu,
         "latency": latency,
         "tuned": tuned,

@@ -213,6 +213,33 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
 int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32_t* starts,
                 uint64_t n, uint32_t length, uint64_t seed, void* stream, fw_tune* best);
 
+/* Results larger than device memory (section 5.2, Eq. 5).  fw_walk_host
+ * runs n queries whose rows go to host memory, in batches of
+ *     B = floor(device_budget_bytes / (2 * (length + 2) * 4))
+ * queries (each of two ping-pong buffers holds a batch's start vertices and
+ * its rows of length + 1 entries; Eq. 5 with M - M_G = the budget), capped at
+ * max_batch_queries when that is non-zero.  Consecutive batches alternate
+ * between two streams, so one batch's device-to-host copy overlaps the next
+ * batch's walk.  Query i has id i: the rows equal fw_walk's. */
+typedef struct fw_batch_opts {
+  uint64_t device_budget_bytes;  /* 0 = the free device memory less 1 GiB */
+  uint64_t max_batch_queries;    /* 0 = no cap */
+  int mode;                      /* fw_mode of each batch (0 = FW_MODE_AUTO) */
+  uint64_t batch_queries;        /* out: B */
+  uint32_t batches;              /* out: number of batches */
+} fw_batch_opts;
+
+/*   starts_host  host, uint32[n]
+ *   out_host     host, uint32[n * (length + 1)], row-major as fw_walk's
+ *   opts         may be NULL (defaults); receives B and the batch count
+ * Allocates two device buffers of B queries, two pinned host staging
+ * buffers and two streams for the call, and blocks until every row is in
+ * out_host.  Errors: as fw_walk (start vertices are checked on the host
+ * first), FW_EINVAL when the budget holds no query, FW_ENOMEM, FW_EHIP. */
+int fw_walk_host(const fw_graph* g, fw_algo algo, const fw_params* params,
+                 const uint32_t* starts_host, uint64_t n, uint32_t length, uint64_t seed,
+                 uint32_t* out_host, fw_batch_opts* opts);
+
 /* Realised hops of a walk result (Alg. 1: a step is one appended vertex):
  * the entries of columns 1..length of the n x (length + 1) row-major device
  * matrix out_paths that are not FW_END, written to *steps (host).  Runs on

@@ -62,6 +62,12 @@ class WalkOpts(ctypes.Structure):
 SAMPLERS = {"its": 0, "dprs": 1, "zprs": 2}
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("device_budget_bytes", ctypes.c_uint64), ("max_batch_queries", ctypes.c_uint64),
+                ("mode", ctypes.c_int), ("batch_queries", ctypes.c_uint64),
+                ("batches", ctypes.c_uint32)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("max_batch_requests", ctypes.c_uint32)]
@@ -85,6 +91,8 @@ def _bind(lib):
                         ctypes.POINTER(WalkOpts)], i32),
         "fw_sync": ([vp, vp], i32),
         "fw_count_steps": ([vp, u64, u32, vp, ctypes.POINTER(u64)], i32),
+        "fw_walk_host": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
+                          ctypes.POINTER(BatchOpts)], i32),
         "fw_autotune": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                          ctypes.POINTER(Tune)], i32),
         "fw_server_create": ([vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], i32),
@@ -268,6 +276,24 @@ def autotune(graph: Graph, algo, prm: Params | None, starts, length: int, seed: 
                             starts.data_ptr(), starts.shape[0], length, seed,
                             _stream_handle(stream), ctypes.byref(best)), "fw_autotune")
     return {k: getattr(best, k) for k, _ in Tune._fields_}
+
+
+def walk_host(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
+              device_budget_bytes: int = 0, max_batch_queries: int = 0, mode="auto"):
+    """Runs the queries of `starts` (host uint32 array) with rows in host
+    memory, in ping-pong batches that fit the device budget.  Returns
+    (rows uint32[n, length + 1], queries per batch, batches)."""
+    st = np.ascontiguousarray(starts, dtype=np.uint32)
+    out = np.empty((st.shape[0], length + 1), dtype=np.uint32)
+    o = BatchOpts()
+    o.device_budget_bytes = device_budget_bytes
+    o.max_batch_queries = max_batch_queries
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    a = ALGOS.get(algo, algo)
+    _check(_lib.fw_walk_host(graph.handle, a, None if prm is None else ctypes.byref(prm),
+                             st.ctypes.data, st.shape[0], length, seed, out.ctypes.data,
+                             ctypes.byref(o)), "fw_walk_host")
+    return out, int(o.batch_queries), int(o.batches)
 
 
 def count_steps(paths, stream=None) -> int:

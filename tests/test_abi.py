@@ -87,3 +87,9 @@ def test_count_steps_rejects_null_on_host():
     assert lib.fw_count_steps(None, 0, 3, None, ctypes.byref(n)) == fw.OK and n.value == 0
     assert lib.fw_count_steps(None, 5, 0, None, ctypes.byref(n)) == fw.OK and n.value == 0
     assert lib.fw_count_steps(None, 1 << 62, 7, None, ctypes.byref(n)) == fw.EINVAL
+
+
+def test_walk_host_checks_arguments_on_host():
+    from paper_2404_08364_amd import flowwalk as fw
+    lib = fw.lib()
+    assert lib.fw_walk_host(None, 0, None, None, 4, 3, 1, None, None) == fw.EINVAL
