@@ -57,15 +57,18 @@ def byte_model(algo: str, weighted: bool, labelled: bool):
     return dict(scan=(1 + (4 if weighted else 0)), emit=8)
 
 
-# Sources the persistent walker kernel is compiled from (and its build flags).
+# Sources the persistent walker kernel is compiled from; its compiler flags
+# are hashed with them.
 WALKER_SOURCES = ["csrc/fw_device.h", "csrc/fw_wave_sampler.h", "csrc/fw_kernels.h",
-                  "csrc/fw_persistent.hip", "build.py"]
+                  "csrc/fw_persistent.hip"]
 
 
 def kernel_source_hash() -> str:
+    from paper_2404_08364_amd import build
     h = hashlib.sha1()
     for rel in WALKER_SOURCES:
         h.update((ROOT / "paper_2404_08364_amd" / rel).read_bytes())
+    h.update(" ".join(build.HIPCC_FLAGS).encode())
     return h.hexdigest()[:12]
 
 
