@@ -81,6 +81,10 @@ def bind(lib):
     lib.fwo_reservoir.restype = ctypes.c_int64
     lib.fwo_walk_sampler.argtypes = [pg, i32, pp, i32, vp, u64, u32, u64, u64, vp]
     lib.fwo_walk_sampler.restype = i32
+    lib.fwo_alias_table.argtypes = [vp, u32, vp, vp]
+    lib.fwo_alias_table.restype = u64
+    lib.fwo_sample_task.argtypes = [i32, vp, u32, u64, u64]
+    lib.fwo_sample_task.restype = ctypes.c_int64
     lib.fwo_scale.argtypes = [u64, u64]
     lib.fwo_scale.restype = u64
     lib.fwo_pick.argtypes = [vp, u64, u64]
@@ -218,6 +222,36 @@ def walk(g, algo, prm, starts, length: int, seed: int, qid_base: int = 0,
     rc, out = walk_status(g, algo, prm, starts, length, seed, qid_base, sampler)
     if rc:
         raise OracleError(rc, "fwo_walk")
+    return out
+
+
+TASK_SAMPLERS = {"its": 0, "dprs": 1, "zprs": 2, "its_buffered": 3, "alias": 4, "rejection": 5}
+RJS_MAX_TRIALS = 1 << 24
+
+
+def alias_table(w):
+    """(T, prob uint64[n], alias uint32[n]) of the sweep construction."""
+    a = np.ascontiguousarray(w, dtype=np.uint32)
+    n = a.shape[0]
+    prob = np.zeros(max(n, 1), dtype=np.uint64)
+    alias = np.zeros(max(n, 1), dtype=np.uint32)
+    T = int(_load().fwo_alias_table(a.ctypes.data, n, prob.ctypes.data, alias.ctypes.data))
+    return T, prob[:n], alias[:n]
+
+
+def sample_task(sampler, w, seed: int, task: int) -> int:
+    a = np.ascontiguousarray(w, dtype=np.uint32)
+    return int(_load().fwo_sample_task(TASK_SAMPLERS.get(sampler, sampler), a.ctypes.data,
+                                       a.shape[0], seed, task))
+
+
+def sample_tasks(sampler, weights, size: int, seed: int) -> np.ndarray:
+    """Picks of every task of the flat weight array (task j = weights[j*size:(j+1)*size])."""
+    a = np.ascontiguousarray(weights, dtype=np.uint32)
+    n = a.shape[0] // size
+    out = np.empty(n, dtype=np.int64)
+    for j in range(n):
+        out[j] = sample_task(sampler, a[j * size:(j + 1) * size], seed, j)
     return out
 
 

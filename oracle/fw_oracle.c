@@ -250,6 +250,108 @@ static uint64_t max_degree(const fwo_graph* g) {
   return m;
 }
 
+uint64_t fwo_alias_table(const uint32_t* w, uint32_t n, uint64_t* prob, uint32_t* alias) {
+  uint64_t T = 0;
+  for (uint32_t i = 0; i < n; ++i) T += w[i];
+  if (T == 0) return 0;
+  for (uint32_t c = 0; c < n; ++c) {
+    prob[c] = T;
+    alias[c] = c;
+  }
+  /* q_i = w_i * n: light when q_i < T, heavy otherwise. */
+  uint32_t i = 0, j = 0;
+  while (i < n && (uint64_t)w[i] * n >= T) ++i;
+  while (j < n && (uint64_t)w[j] * n < T) ++j;
+  if (j >= n) return T; /* cannot happen: some item is at least the mean */
+  uint64_t rem = (uint64_t)w[j] * n; /* mass left in heavy j */
+  while (j < n) {
+    if (rem > T) {
+      if (i >= n) break;
+      uint64_t q = (uint64_t)w[i] * n;
+      prob[i] = q;
+      alias[i] = j;
+      rem -= T - q;
+      do ++i; while (i < n && (uint64_t)w[i] * n >= T);
+    } else {
+      uint32_t nj = j + 1;
+      while (nj < n && (uint64_t)w[nj] * n < T) ++nj;
+      prob[j] = rem;
+      alias[j] = nj < n ? nj : j;
+      if (nj < n) rem = (uint64_t)w[nj] * n - (T - rem);
+      j = nj;
+    }
+  }
+  return T;
+}
+
+static uint64_t mulhi64(uint64_t a, uint64_t b) {
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+}
+
+int64_t fwo_sample_task(int sampler, const uint32_t* w, uint32_t size, uint64_t seed,
+                        uint64_t task) {
+  uint64_t T = 0, wmax = 0;
+  for (uint32_t i = 0; i < size; ++i) {
+    T += w[i];
+    if (w[i] > wmax) wmax = w[i];
+  }
+  if (T == 0) return -1;
+  uint64_t key[2] = {seed, 0}, out[4];
+  if (sampler == FWO_TASK_ITS || sampler == FWO_TASK_ITS_BUFFERED) {
+    uint64_t ctr[4] = {task, 0, 0, 0};
+    fwo_philox4x64_10(ctr, key, out);
+    uint64_t r = mulhi64(out[0], T), prefix = 0;
+    for (uint32_t i = 0; i < size; ++i) {
+      prefix += w[i];
+      if (prefix > r) return i;
+    }
+    return -1;
+  }
+  if (sampler == FWO_TASK_DPRS || sampler == FWO_TASK_ZPRS) {
+    uint64_t *wb = malloc(size * sizeof(uint64_t)), *ub = malloc(size * sizeof(uint64_t)),
+             *ob = malloc(size * sizeof(uint64_t));
+    int64_t pick = -1;
+    if (wb && ub && ob) {
+      for (uint32_t i = 0; i < size; ++i) {
+        wb[i] = w[i];
+        ub[i] = fwo_entry_draw(seed, task, 0, i);
+        ob[i] = i;
+      }
+      if (sampler == FWO_TASK_ZPRS) fwo_zigzag_order(size, FWO_ZPRS_LANES, ob);
+      pick = fwo_reservoir(wb, ub, ob, size);
+    }
+    free(wb);
+    free(ub);
+    free(ob);
+    return pick;
+  }
+  if (sampler == FWO_TASK_ALIAS) {
+    uint64_t* prob = malloc(size * sizeof(uint64_t));
+    uint32_t* alias = malloc(size * sizeof(uint32_t));
+    int64_t pick = -1;
+    if (prob && alias) {
+      fwo_alias_table(w, size, prob, alias);
+      uint64_t ctr[4] = {task, 0, 0, 2};
+      fwo_philox4x64_10(ctr, key, out);
+      uint64_t c = mulhi64(out[0], size);
+      pick = mulhi64(out[1], T) < prob[c] ? (int64_t)c : (int64_t)alias[c];
+    }
+    free(prob);
+    free(alias);
+    return pick;
+  }
+  if (sampler == FWO_TASK_REJECTION) {
+    for (uint64_t k = 0; k < FWO_RJS_MAX_TRIALS; ++k) {
+      uint64_t ctr[4] = {task, k, 0, 3};
+      fwo_philox4x64_10(ctr, key, out);
+      uint64_t c = mulhi64(out[0], size);
+      if (mulhi64(out[1], wmax) < w[c]) return (int64_t)c;
+    }
+    return -1;
+  }
+  return -1;
+}
+
 /* Scratch of one walker: weights, entry words and a visiting order, each
  * max_degree long. */
 typedef struct {

@@ -128,6 +128,43 @@ void fwo_zigzag_order(uint64_t d, uint32_t k, uint64_t* order);
  * the last selected entry, or -1 when every weight is 0. */
 int64_t fwo_reservoir(const uint64_t* w, const uint64_t* u, const uint64_t* order, uint64_t d);
 
+/* Sampler microbenchmark tasks (section 6.5's comparison of sampling
+ * methods): task j picks one index of the `size` weights w[0 .. size) with
+ * chance w_i / T, T = sum(w), or returns -1 when T = 0.  Draws are keyed by
+ * (seed, task j):
+ *   ITS            word 0 of Philox(counter (j, 0, 0, 0)): r = floor(u T / 2^64),
+ *                  first inclusive prefix above r (the buffered variant picks
+ *                  the same index from a stored prefix array);
+ *   DPRS / ZPRS    entry i's word = word i mod 4 of Philox(j, 0, i / 4, 1);
+ *   ALIAS          Vose's alias table built by the sweep below, then column
+ *                  c = floor(u0 size / 2^64) and, with words u0, u1 of
+ *                  Philox(j, 0, 0, 2), c itself when floor(u1 T / 2^64) < prob[c],
+ *                  else alias[c];
+ *   REJECTION      trial k uses words u0, u1 of Philox(j, k, 0, 3): candidate
+ *                  c = floor(u0 size / 2^64), accepted when
+ *                  floor(u1 wmax / 2^64) < w_c; after FWO_RJS_MAX_TRIALS
+ *                  rejections the task returns -1. */
+#define FWO_TASK_ITS 0
+#define FWO_TASK_DPRS 1
+#define FWO_TASK_ZPRS 2
+#define FWO_TASK_ITS_BUFFERED 3
+#define FWO_TASK_ALIAS 4
+#define FWO_TASK_REJECTION 5
+#define FWO_RJS_MAX_TRIALS (1u << 24)
+
+/* Alias table of w[0 .. n) with column capacity T = sum(w) in units of
+ * w_i * n (so every probability is an exact integer): a sweep over the light
+ * items (w_i n < T) and the heavy items (w_i n >= T), both in index order.
+ * The current heavy item fills the light items one after the other; once its
+ * remaining mass is at most T it becomes a column of its own, filled from the
+ * next heavy item.  prob[c] = the part of column c kept by c (<= T), alias[c]
+ * = the item that owns the rest.  Returns T (0: the table is not built). */
+uint64_t fwo_alias_table(const uint32_t* w, uint32_t n, uint64_t* prob, uint32_t* alias);
+
+/* One task of the given sampler over w[0 .. size); -1 when nothing is picked. */
+int64_t fwo_sample_task(int sampler, const uint32_t* w, uint32_t size, uint64_t seed,
+                        uint64_t task);
+
 /* Walks n queries.  Query i has id qid_base + i and starts at starts[i];
  * row i of out_paths (length + 1 entries) receives its path. */
 int fwo_walk(const fwo_graph* g, int algo, const fwo_params* p, const uint32_t* starts,

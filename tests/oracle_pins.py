@@ -440,7 +440,7 @@ def pin_reservoir_extremes():
         assert gotm == (pos[0] if pos else -1)
 
 
-def pin_reservoir_distribution(n=200_000):
+def pin_reservoir_distribution(n=100_000):
     """Algorithm 2 picks entry i with chance w_i / T in any visiting order
     (Proposition 1), here with words from numpy's default generator."""
     from scipy.stats import chisquare
@@ -504,7 +504,7 @@ def pin_reservoir_walks_rebuilt():
             assert rows[i].tolist() == exp, (sampler, i, rows[i], exp)
 
 
-def pin_reservoir_hop_distribution(n=300_000):
+def pin_reservoir_hop_distribution(n=150_000):
     """One hop from a 700-neighbour hub: both samplers pick neighbour i with
     chance w_i / T (chi-square), while ZPRS's picks differ from DPRS's."""
     from scipy.stats import chisquare
@@ -521,6 +521,119 @@ def pin_reservoir_hop_distribution(n=300_000):
     assert (got["dprs"] != got["zprs"]).mean() > 0.5
 
 
+def pin_alias_golden():
+    import json
+    from pathlib import Path
+    cases = json.loads((Path(__file__).parent / "golden" / "alias_table.json").read_text())
+    for c in cases["cases"]:
+        T, prob, alias = oracle.alias_table(c["w"])
+        assert T == c["T"], c
+        if T:
+            assert prob.tolist() == c["prob"] and alias.tolist() == c["alias"], (c, prob, alias)
+
+
+def pin_alias_mass_identity():
+    """What makes an alias table exact: column c keeps prob[c] <= T of its
+    own item and gives T - prob[c] to alias[c], so item i owns
+    prob[i] + sum over {c != i : alias[c] = i} of (T - prob[c]) = w_i * n."""
+    rng = np.random.default_rng(29)
+    for trial in range(300):
+        n = int(rng.integers(1, 300))
+        kind = trial % 3
+        if kind == 0:
+            w = rng.integers(0, 10, n)
+        elif kind == 1:
+            w = np.floor(rng.lognormal(0, 2.5, n)).astype(np.int64)
+        else:
+            w = rng.integers(0, 1 << 32, n, dtype=np.uint64) * (rng.random(n) < 0.3)
+        w = w.astype(np.uint32)
+        T, prob, alias = oracle.alias_table(w)
+        assert T == int(w.astype(np.uint64).sum())
+        if T == 0:
+            continue
+        own = [int(p) for p in prob]
+        assert max(own) <= T and min(own) >= 0
+        mass = own[:]
+        for c in range(n):
+            if int(alias[c]) != c:
+                mass[int(alias[c])] += T - own[c]
+            else:
+                assert own[c] == T, (c, own[c], T)
+        assert mass == [int(x) * n for x in w], trial
+
+
+def _task_weights(size, kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        return rng.integers(1, 256, size).astype(np.uint32)
+    w = np.floor(rng.lognormal(0, 1.5, size) * 8).astype(np.uint32)
+    w[size // 3] = 0
+    return w
+
+
+def pin_task_samplers_law(n=60_000):
+    """Every microbenchmark sampler picks index i with chance w_i / T
+    (chi-square over n tasks with the same weights and different ids)."""
+    from scipy.stats import chisquare
+    w = _task_weights(24, "lognormal", 3)
+    T = float(w.astype(np.float64).sum())
+    for sampler in ["its", "dprs", "zprs", "its_buffered", "alias", "rejection"]:
+        picks = [oracle.sample_task(sampler, w, 31, j) for j in range(n)]
+        counts = np.bincount(picks, minlength=w.shape[0])
+        nz = w > 0
+        assert counts[~nz].sum() == 0, sampler
+        assert chisquare(counts[nz], w[nz] / T * n).pvalue > 1e-4, (sampler, counts)
+
+
+def _py_task(sampler, w, seed, task):
+    """Tasks rebuilt from numpy's Philox and Python integers; the alias
+    table comes from the oracle (pinned above), the reservoir samplers reuse
+    the rebuilt walk step."""
+    w = [int(x) for x in w]
+    n, T, wmax = len(w), sum(w), max(w)
+    if T == 0:
+        return -1
+    if sampler in ("its", "its_buffered"):
+        r = (_numpy_philox_block([task, 0, 0, 0], [seed, 0])[0] * T) >> 64
+        acc = 0
+        for i, x in enumerate(w):
+            acc += x
+            if acc > r:
+                return i
+    if sampler == "alias":
+        _, prob, alias = oracle.alias_table(w)
+        u = _numpy_philox_block([task, 0, 0, 2], [seed, 0])
+        c = (u[0] * n) >> 64
+        return c if (u[1] * T) >> 64 < int(prob[c]) else int(alias[c])
+    if sampler == "rejection":
+        for k in range(1 << 24):
+            u = _numpy_philox_block([task, k, 0, 3], [seed, 0])
+            c = (u[0] * n) >> 64
+            if (u[1] * wmax) >> 64 < w[c]:
+                return c
+        return -1
+    raise ValueError(sampler)
+
+
+def pin_task_samplers_rebuilt():
+    for size, kind in [(1, "uniform"), (5, "lognormal"), (40, "lognormal"), (300, "uniform")]:
+        w = _task_weights(size, kind, size)
+        for sampler in ["its", "its_buffered", "alias", "rejection"]:
+            for task in [0, 1, 77, 123456]:
+                assert oracle.sample_task(sampler, w, 5, task) == _py_task(sampler, w, 5, task), \
+                    (sampler, size, task)
+    # uniform weights: the first rejection trial is always accepted
+    w = np.full(50, 7, np.uint32)
+    for task in range(20):
+        u = _numpy_philox_block([task, 0, 0, 3], [9, 0])
+        assert oracle.sample_task("rejection", w, 9, task) == (u[0] * 50) >> 64
+    for sampler in oracle.TASK_SAMPLERS:
+        assert oracle.sample_task(sampler, np.zeros(9, np.uint32), 1, 1) == -1
+        one = np.zeros(9, np.uint32)
+        one[6] = 3
+        assert all(oracle.sample_task(sampler, one, 1, t) == 6 for t in range(10)), sampler
+
+
 ALL_PINS = [pin_philox_kat, pin_philox_numpy, pin_draw_keying, pin_scale_closed_form,
             pin_pick_bruteforce, pin_hand_weights, pin_walk_rebuilt, pin_chi2_paths, pin_identities,
             pin_regular_uniform, pin_path_graph_edges, pin_errors,
@@ -528,4 +641,10 @@ ALL_PINS = [pin_philox_kat, pin_philox_numpy, pin_draw_keying, pin_scale_closed_
             pin_ppr_rebuilt, pin_ppr_length_distribution, pin_ppr_limits,
             pin_entry_draw_keying, pin_zigzag_golden, pin_reservoir_extremes,
             pin_reservoir_distribution, pin_reservoir_walks_rebuilt,
-            pin_reservoir_hop_distribution]
+            pin_reservoir_hop_distribution, pin_alias_golden, pin_alias_mass_identity,
+            pin_task_samplers_law, pin_task_samplers_rebuilt]
+
+# The statistical pins take seconds each; a planted mistake is looked for
+# with the exact pins first.
+SLOW_PINS = [pin_chi2_paths, pin_reservoir_distribution, pin_reservoir_hop_distribution,
+             pin_task_samplers_law]
