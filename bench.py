@@ -303,6 +303,50 @@ def sampler_sweep():
     return rows
 
 
+def task_sweep(total_log2=28):
+    """Sampler microbenchmark: 2^28 uint32 weights (1 GiB) split into tasks
+    of 2^k entries, one pick per task, for each sampler; weights U[1,255]
+    and log-normal (mu 0, sigma 1, 2, 3; scaled by 16) as in the comparison
+    with rejection sampling.  The alias table is built on one lane, so it
+    runs up to 2^12 entries only."""
+    import torch
+    from paper_2404_08364_amd import flowwalk as fw
+    rng = np.random.default_rng(5)
+    n_all = 1 << total_log2
+    dists = {"uniform": rng.integers(1, 256, n_all).astype(np.uint32)}
+    for sg in (1, 2, 3):
+        x = np.minimum(np.floor(rng.lognormal(0, sg, n_all) * 16), 2**32 - 1)
+        dists[f"lognormal{sg}"] = np.maximum(x, 1).astype(np.uint32)
+    rows = []
+    for name, w in dists.items():
+        wt = torch.from_numpy(w.view(np.int32)).cuda()
+        for k in range(4, 21, 2):
+            size = 1 << k
+            res = dict(weights=name, size=size, tasks=n_all // size)
+            for smp in ["its", "dprs", "zprs", "its_buffered", "alias", "rejection"]:
+                if smp == "alias" and size > 4096:
+                    continue
+                if name != "uniform" and smp not in ("its", "dprs", "rejection"):
+                    continue
+                picks = torch.empty(n_all // size, dtype=torch.int32, device="cuda")
+                ms = []
+                for rep in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    fw.sample_tasks(smp, wt, size, 11 + rep, picks=picks)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    if rep:
+                        ms.append(e0.elapsed_time(e1))
+                t = float(np.median(ms))
+                res[smp] = dict(ms=t, gelem_per_s=n_all / (t / 1e3) / 1e9)
+            rows.append(res)
+            print(json.dumps(res), flush=True)
+        del wt
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +369,8 @@ def main():
                     help="time only the first N queries of the workload (0 = all)")
     ap.add_argument("--host-batches", type=int, default=0,
                     help="also time fw_walk_host (rows to host memory) in this many batches")
+    ap.add_argument("--task-sweep", action="store_true",
+                    help="only run the sampler microbenchmark (2^28 weights split into tasks)")
     ap.add_argument("--sampler-sweep", action="store_true",
                     help="only time ITS / DPRS / ZPRS hops by degree on star graphs")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -347,6 +393,9 @@ def main():
 
     if args.sampler_sweep:
         sampler_sweep()
+        return
+    if args.task_sweep:
+        task_sweep()
         return
 
     if args.gpus != 1:

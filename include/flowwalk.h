@@ -251,6 +251,48 @@ int fw_walk_host(const fw_graph* g, fw_algo algo, const fw_params* params,
 int fw_count_steps(const uint32_t* out_paths, uint64_t n, uint32_t length, void* stream,
                    uint64_t* steps);
 
+/* Sampler microbenchmark (the comparison of sampling methods, section 6.5,
+ * and of rejection sampling, Appendix C).  n_tasks independent tasks; task j
+ * picks one index i of the weights w = weights[j * size .. (j + 1) * size)
+ * with chance w_i / T, T = sum(w), and writes it to picks[j] (FW_END when
+ * T = 0, or when REJECTION rejected FW_RJS_MAX_TRIALS candidates).
+ *   FW_TASK_ITS           the walkers' bufferless two-pass pick: word 0 u of
+ *                         Philox4x64-10(counter (j, 0, 0, 0), key (seed, 0)),
+ *                         r = floor(u T / 2^64), first prefix above r;
+ *   FW_TASK_DPRS / ZPRS   the reservoir samplers of fw_sampler, entry i's word
+ *                         from counter (j, 0, i / 4, 1);
+ *   FW_TASK_ITS_BUFFERED  the same pick as FW_TASK_ITS from an O(size) array
+ *                         of prefix sums (a device scratch slice per task in
+ *                         flight) and a binary search;
+ *   FW_TASK_ALIAS         Vose's alias table (capacities in units of w_i *
+ *                         size, so exact) built by an index-order sweep:
+ *                         the current heavy item fills the light items in
+ *                         order, and once its remaining mass is at most T it
+ *                         becomes a column filled from the next heavy item;
+ *                         then words u0, u1 of counter (j, 0, 0, 2) pick
+ *                         column c = floor(u0 size / 2^64), kept when
+ *                         floor(u1 T / 2^64) < prob[c], else its alias;
+ *   FW_TASK_REJECTION     trial k: words u0, u1 of counter (j, k, 0, 3),
+ *                         candidate c = floor(u0 size / 2^64), accepted when
+ *                         floor(u1 wmax / 2^64) < w_c; the first accepted
+ *                         trial wins.
+ *   weights  device, uint32[n_tasks * size]; picks  device, uint32[n_tasks]
+ * Runs on `stream` and blocks until done; the buffered samplers allocate at
+ * most 8 GiB of scratch for the call.  Errors: FW_EINVAL (unknown sampler,
+ * size 0, NULL pointers, size overflow), FW_ENOMEM, FW_EHIP. */
+typedef enum {
+  FW_TASK_ITS = 0,
+  FW_TASK_DPRS = 1,
+  FW_TASK_ZPRS = 2,
+  FW_TASK_ITS_BUFFERED = 3,
+  FW_TASK_ALIAS = 4,
+  FW_TASK_REJECTION = 5
+} fw_task_sampler;
+#define FW_RJS_MAX_TRIALS (1u << 24)
+
+int fw_sample_tasks(int sampler, const uint32_t* weights, uint64_t n_tasks, uint32_t size,
+                    uint64_t seed, uint32_t* picks, void* stream);
+
 /* Waits for `stream` (a hipStream_t, NULL = null stream) and returns the
  * status that kernels of graph g detected since the last check (FW_EINVAL
  * for a start vertex >= V), clearing it. */

@@ -91,6 +91,7 @@ def _bind(lib):
                         ctypes.POINTER(WalkOpts)], i32),
         "fw_sync": ([vp, vp], i32),
         "fw_count_steps": ([vp, u64, u32, vp, ctypes.POINTER(u64)], i32),
+        "fw_sample_tasks": ([i32, vp, u64, u32, u64, vp, vp], i32),
         "fw_walk_host": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                           ctypes.POINTER(BatchOpts)], i32),
         "fw_autotune": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
@@ -294,6 +295,26 @@ def walk_host(graph: Graph, algo, prm: Params | None, starts, length: int, seed:
                              st.ctypes.data, st.shape[0], length, seed, out.ctypes.data,
                              ctypes.byref(o)), "fw_walk_host")
     return out, int(o.batch_queries), int(o.batches)
+
+
+TASK_SAMPLERS = {"its": 0, "dprs": 1, "zprs": 2, "its_buffered": 3, "alias": 4, "rejection": 5}
+
+
+def sample_tasks(sampler, weights, size: int, seed: int, picks=None, stream=None):
+    """Sampler microbenchmark: task j picks an index of weights[j*size:(j+1)*size]
+    (a contiguous int32/uint32 device tensor); returns the int32 picks (-1 =
+    END)."""
+    import torch
+    weights = weights.contiguous()
+    n = weights.numel() // size
+    if picks is None:
+        picks = torch.empty(n, dtype=torch.int32, device=weights.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(weights.device)
+    smp = TASK_SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+    _check(_lib.fw_sample_tasks(smp, weights.data_ptr(), n, size, seed, picks.data_ptr(),
+                                _stream_handle(stream)), "fw_sample_tasks")
+    return picks
 
 
 def count_steps(paths, stream=None) -> int:

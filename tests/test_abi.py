@@ -93,3 +93,12 @@ def test_walk_host_checks_arguments_on_host():
     from paper_2404_08364_amd import flowwalk as fw
     lib = fw.lib()
     assert lib.fw_walk_host(None, 0, None, None, 4, 3, 1, None, None) == fw.EINVAL
+
+
+def test_sample_tasks_checks_arguments_on_host():
+    from paper_2404_08364_amd import flowwalk as fw
+    lib = fw.lib()
+    assert lib.fw_sample_tasks(9, None, 4, 3, 1, None, None) == fw.EINVAL
+    assert lib.fw_sample_tasks(0, None, 0, 3, 1, None, None) == fw.OK
+    assert lib.fw_sample_tasks(0, None, 4, 0, 1, None, None) == fw.EINVAL
+    assert lib.fw_sample_tasks(0, None, 4, 3, 1, None, None) == fw.EINVAL
