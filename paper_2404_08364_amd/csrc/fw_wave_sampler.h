@@ -67,7 +67,9 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
     const uint64_t gb = lo + g * sp.gsz;
     const uint64_t ge = min(gb + sp.gsz, lo + len);
     uint64_t acc = 0;
-#pragma unroll 2
+    // Not unrolled: at eight wavefronts per SIMD occupancy hides the load
+    // latency, and the second copy of the evaluator would spill registers.
+#pragma unroll 1
     for (uint64_t q = gb + lane; q < ge; q += kWave) {
       uint64_t w[4];
       quad_weights(ev, s, q, w);
