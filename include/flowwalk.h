@@ -100,7 +100,9 @@ typedef struct fw_graph_info {
  * optional per-edge weights (host uint32[n_edges], NULL = all 1) and labels
  * (host uint8[n_edges], NULL = none), into HBM of the current device.  The
  * library owns the device copy; the caller keeps its host arrays.
- * Errors: FW_EINVAL (NULL pointers, malformed CSR), FW_ENOMEM, FW_EHIP. */
+ * Every degree must be below 2^28.
+ * Errors: FW_EINVAL (NULL pointers, malformed CSR, a degree of 2^28 or
+ * more), FW_ENOMEM, FW_EHIP. */
 int fw_graph_upload(const fw_csr* csr, const uint32_t* weights, const uint8_t* labels,
                     fw_graph** out);
 
@@ -279,7 +281,7 @@ int fw_count_steps(const uint32_t* out_paths, uint64_t n, uint32_t length, void*
  *   weights  device, uint32[n_tasks * size]; picks  device, uint32[n_tasks]
  * Runs on `stream` and blocks until done; the buffered samplers allocate at
  * most 8 GiB of scratch for the call.  Errors: FW_EINVAL (unknown sampler,
- * size 0, NULL pointers, size overflow), FW_ENOMEM, FW_EHIP. */
+ * size 0 or >= 2^28, NULL pointers, size overflow), FW_ENOMEM, FW_EHIP. */
 typedef enum {
   FW_TASK_ITS = 0,
   FW_TASK_DPRS = 1,

@@ -10,6 +10,9 @@ namespace fw {
 
 constexpr uint32_t kEnd = 0xFFFFFFFFu;
 constexpr int kWave = 64;
+// Degrees (and sampler task sizes) stay below 2^28, so that quad offsets
+// within a neighbour slice fit in 32 bits.
+constexpr uint64_t kMaxDegree = 1ull << 28;
 
 enum Algo : int { kDeepWalk = 0, kNode2Vec = 1, kMetaPath = 2, kPPR = 3 };
 
@@ -158,6 +161,10 @@ __device__ __forceinline__ uint32_t uniform32(uint32_t v) {
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t x) { return readlane64(wave_incl_scan(x), 63); }
 
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
+  return readlane32(wave_incl_scan32(x), 63);
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int first_lane(uint64_t mask) { return (int)__builtin_ctzll(mask); }
@@ -244,6 +251,9 @@ struct Eval {
   bool first;
   // MetaPath: label this hop must carry.
   uint32_t want;
+  // First entry of the current slice's quad run (a multiple of 4): quad q
+  // of the run holds the absolute entries qa + 4q .. qa + 4q + 3.
+  uint64_t qa;
 
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
     const uint64_t e = o + i;
@@ -262,13 +272,16 @@ struct Eval {
     }
   }
 
-  // Weights of the four entries at absolute CSR positions [p, p + 4), p a
-  // multiple of 4 (the arrays are padded so that a quad never ends past the
-  // allocation).  Entries outside the current slice are masked by the caller.
-  __device__ __forceinline__ void quad(uint64_t p, uint64_t out[4]) const {
+  // Weights of quad q of the run at qa (the arrays are padded so that a
+  // quad never ends past the allocation), entries outside the slice
+  // included: the caller masks them.  The offset from the uniform base qa is
+  // 32-bit (slices are < 2^28 entries), so each load is one scalar base plus
+  // one vector offset.
+  __device__ __forceinline__ void quad(uint32_t q, uint64_t out[4]) const {
     uint32_t wq[4] = {1u, 1u, 1u, 1u};
     if (WEIGHTED) {
-      const uint4 v = *reinterpret_cast<const uint4*>(w + p);
+      const uint4 v = *reinterpret_cast<const uint4*>(
+          reinterpret_cast<const char*>(w + qa) + q * 16u);
       wq[0] = v.x; wq[1] = v.y; wq[2] = v.z; wq[3] = v.w;
     }
     if (ALGO == kNode2Vec) {
@@ -277,7 +290,8 @@ struct Eval {
         for (int j = 0; j < 4; ++j) out[j] = wq[j];
         return;
       }
-      const uint4 a = *reinterpret_cast<const uint4*>(adj + p);
+      const uint4 a = *reinterpret_cast<const uint4*>(
+          reinterpret_cast<const char*>(adj + qa) + q * 16u);
       const uint32_t u[4] = {a.x, a.y, a.z, a.w};
       bool in[4];
       mem.contains4(u, in);
@@ -291,7 +305,8 @@ struct Eval {
         out[j] = (uint64_t)wq[j] * f;
       }
     } else if (ALGO == kMetaPath) {
-      const uint32_t l = *reinterpret_cast<const uint32_t*>(lab + p);
+      const uint32_t l = *reinterpret_cast<const uint32_t*>(
+          reinterpret_cast<const char*>(lab + qa) + q * 4u);
 #pragma unroll
       for (int j = 0; j < 4; ++j) out[j] = (((l >> (8 * j)) & 0xFFu) == want) ? wq[j] : 0ull;
     } else {

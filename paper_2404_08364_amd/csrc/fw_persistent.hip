@@ -43,8 +43,9 @@ __device__ __forceinline__ uint32_t log2_ceil(uint64_t x) {
 
 __device__ __forceinline__ uint32_t max4(uint4 v) { return max(max(v.x, v.y), max(v.z, v.w)); }
 
+// u is one of the four cells: the smallest XOR with u is 0.
 __device__ __forceinline__ bool has4(uint4 v, uint32_t u) {
-  return (v.x == u) | (v.y == u) | (v.z == u) | (v.w == u);
+  return min(min(v.x ^ u, v.y ^ u), min(v.z ^ u, v.w ^ u)) == 0u;
 }
 
 // Membership in N(prev) for one node2vec hop, by a wave-uniform mode:
@@ -62,8 +63,9 @@ struct MemberAny {
   const uint32_t* __restrict__ adj;
   uint64_t po, pd;
 
+  // base is a multiple of 4 cells, so a bucket is one aligned 16-byte read.
   __device__ __forceinline__ uint4 bucket(uint32_t b) const {
-    return *reinterpret_cast<const uint4*>(&fw_dyn_lds[base + 4 * b]);
+    return reinterpret_cast<const uint4*>(fw_dyn_lds)[(base >> 2) + b];
   }
   __device__ __forceinline__ bool probe_rest(uint32_t u, uint32_t b) const {
     for (;;) {
@@ -197,39 +199,43 @@ template <class E>
 __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSlice& s,
                                                        const GroupSplit& sp, const Table& tb,
                                                        int lane) {
-  const uint32_t* __restrict__ pr = ev.adj + tb.po;
+  const char* __restrict__ wrun = reinterpret_cast<const char*>(ev.w + s.a);
+  const char* __restrict__ arun = reinterpret_cast<const char*>(ev.adj + s.a);
   uint64_t cursor = 0;
   bool global = false;
   uint64_t mine = 0;
-  for (uint64_t g = 0; g < sp.groups; ++g) {
-    const uint64_t gb = g * sp.gsz;
-    const uint64_t ge = min(gb + sp.gsz, s.nq);
+  for (uint32_t g = 0; g < sp.groups; ++g) {
+    const uint32_t gb = g * sp.gsz;
+    const uint32_t ge = min(gb + sp.gsz, s.nq);
     uint64_t acc = 0;
-    for (uint64_t c0 = gb; c0 < ge; c0 += kWave) {
-      const uint64_t q = c0 + lane;
+    for (uint32_t c0 = gb; c0 < ge; c0 += kWave) {
+      const uint32_t q = c0 + lane;
       const bool valid = q < ge;
-      const uint64_t p = s.a + 4 * (valid ? q : c0);
+      const uint32_t qq = valid ? q : c0;
+      uint32_t keep = valid ? 0xFu : 0u;
+      if (valid && (qq == 0 || qq + 1 == s.nq)) {
+        keep = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) keep |= s.inside(qq, j) ? (1u << j) : 0u;
+      }
       uint32_t wq[4] = {1u, 1u, 1u, 1u};
       if (ev.w != nullptr) {
-        const uint4 v = *reinterpret_cast<const uint4*>(ev.w + p);
+        const uint4 v = *reinterpret_cast<const uint4*>(wrun + qq * 16u);
         wq[0] = v.x; wq[1] = v.y; wq[2] = v.z; wq[3] = v.w;
       }
-      const uint4 a = *reinterpret_cast<const uint4*>(ev.adj + p);
+      const uint4 a = *reinterpret_cast<const uint4*>(arun + qq * 16u);
       const uint32_t key[4] = {a.x, a.y, a.z, a.w};
-      bool live[4];
       uint32_t kmax = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        live[j] = valid && p + j >= s.o && p + j < s.o + s.d;
-        if (live[j]) kmax = max(kmax, key[j]);
-      }
+      for (int j = 0; j < 4; ++j) kmax = ((keep >> j) & 1u) ? max(kmax, key[j]) : kmax;
       kmax = wave_max32(kmax);
       bool in[4] = {false, false, false, false};
       if (!global) {
         // Stage N(prev)[cursor, cursor + W): the entries <= kmax (a prefix,
         // N(prev) being sorted).
-        uint32_t W = 0;
-        uint64_t below = 0;  // staged entries < kmax
+        const uint32_t* __restrict__ pr = ev.adj + tb.po + cursor;
+        const uint64_t left = tb.pd - cursor;  // entries of N(prev) from the cursor
+        uint32_t W = 0, below = 0;              // staged entries <= kmax / < kmax
         for (;;) {
           if (W + 4 * kWave > tb.cells) {  // window larger than the region
             global = true;
@@ -238,14 +244,15 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
           uint32_t cnt_le = 0, cnt_lt = 0;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const uint64_t idx = cursor + W + 4 * lane + j;
-            const uint32_t v = idx < tb.pd ? pr[idx] : kEnd;
-            cnt_le += (idx < tb.pd && v <= kmax) ? 1u : 0u;
-            cnt_lt += (idx < tb.pd && v < kmax) ? 1u : 0u;
-            fw_dyn_lds[tb.base + W + 4 * lane + j] = v;
+            const uint32_t k = W + 4 * lane + j;
+            const bool in_row = k < left;
+            const uint32_t v = in_row ? pr[k] : kEnd;
+            cnt_le += (in_row && v <= kmax) ? 1u : 0u;
+            cnt_lt += (in_row && v < kmax) ? 1u : 0u;
+            fw_dyn_lds[tb.base + k] = v;
           }
-          const uint32_t n_le = (uint32_t)wave_sum(cnt_le);
-          below += wave_sum(cnt_lt);
+          const uint32_t n_le = wave_sum32(cnt_le);
+          below += wave_sum32(cnt_lt);
           W += n_le;
           if (n_le < 4 * kWave) break;
         }
@@ -262,11 +269,12 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
       for (int j = 0; j < 4; ++j) {
         const bool is_ret = key[j] == ev.prev;
         const uint32_t f = ev.f_out + ((in[j] && !is_ret) ? d_in : 0u) + (is_ret ? d_ret : 0u);
-        acc += live[j] ? (uint64_t)wq[j] * f : 0ull;
+        const uint32_t wj = ((keep >> j) & 1u) ? wq[j] : 0u;
+        acc += (uint64_t)wj * f;
       }
     }
     const uint64_t tot = wave_sum(acc);
-    if ((uint64_t)lane == g) mine = tot;
+    if ((uint32_t)lane == g) mine = tot;
   }
   return mine;
 }
@@ -453,8 +461,9 @@ k_walk_persistent(
       tb.kind = 0;
       tb.po = tb.pd = 0;
       if (ALGO == kNode2Vec && t > 0) {
-        tb.po = g.off[prev];
-        tb.pd = g.off[prev + 1] - tb.po;
+        // Wave-uniform: kept in scalar registers.
+        tb.po = uniform64(g.off[prev]);
+        tb.pd = uniform64(g.off[prev + 1]) - tb.po;
         build_table(tb, g.adj, d, lane);
       }
       const uint64_t u = philox_draw(R.seed, R.qid_base + qid, t);
@@ -480,7 +489,7 @@ k_walk_persistent(
           const uint64_t m = ballot(incl > r);
           const int gs = m ? first_lane(m) : (int)sp.groups - 1;
           r -= readlane64(incl - mine, gs);
-          const uint64_t lo = (uint64_t)gs * sp.gsz;
+          const uint32_t lo = (uint32_t)gs * sp.gsz;
           idx = (int64_t)wave_locate(ev, qs, lo, min(sp.gsz, qs.nq - lo), r);
         }
       } else {

@@ -195,6 +195,9 @@ int fw_graph_upload(const fw_csr* csr, const uint32_t* weights, const uint8_t* l
     return true;
   });
   if (!ok) return fail(FW_EINVAL, "malformed CSR (offsets, id range or row order)");
+  // The samplers index a neighbour slice with 32-bit quad offsets.
+  if (max_deg.load() >= fw::kMaxDegree)
+    return fail(FW_EINVAL, "a vertex has 2^28 or more neighbours");
 
   fw_graph* g = new (std::nothrow) fw_graph();
   if (!g) return fail(FW_ENOMEM, "host allocation");

@@ -205,12 +205,12 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
 // Pass-1 partition of a hub slice of nq quads: wavefront w owns 64-quad
 // chunks [c0, c1).
 struct HubPart {
-  uint64_t lo, len;
-  __device__ __forceinline__ HubPart(uint64_t nq, int w, int nw) {
-    const uint64_t chunks = (nq + kWave - 1) / kWave;
-    const uint64_t c0 = chunks * w / nw, c1 = chunks * (w + 1) / nw;
+  uint32_t lo, len;
+  __device__ __forceinline__ HubPart(uint32_t nq, int w, int nw) {
+    const uint32_t chunks = (nq + kWave - 1) / kWave;
+    const uint32_t c0 = chunks * w / nw, c1 = chunks * (w + 1) / nw;
     lo = c0 * kWave;
-    const uint64_t hi = min(c1 * kWave, nq);
+    const uint32_t hi = min(c1 * kWave, nq);
     len = hi > lo ? hi - lo : 0;
   }
 };
@@ -228,7 +228,8 @@ __device__ __forceinline__ void hub_hop(const E& ev, PoolLds& P, int s, uint64_t
   {
     const HubPart part(qs.nq, wave, NW);
     uint64_t mine = 0;
-    if (part.len) mine = wave_group_totals(ev, qs, part.lo, part.len, GroupSplit(part.len));
+    if (part.len)
+      mine = wave_group_totals(bind_quads(ev, qs), qs, part.lo, part.len, GroupSplit(part.len));
     P.gt[wave * kWave + lane] = mine;
   }
   __syncthreads();
@@ -257,9 +258,9 @@ __device__ __forceinline__ void hub_hop(const E& ev, PoolLds& P, int s, uint64_t
     }
     const HubPart part(qs.nq, e / kWave, NW);
     const GroupSplit sp(part.len);
-    const uint64_t gi = (uint64_t)(e % kWave);
-    const uint64_t gb = part.lo + gi * sp.gsz;
-    const uint64_t glen = min(sp.gsz, part.len - gi * sp.gsz);
+    const uint32_t gi = (uint32_t)(e % kWave);
+    const uint32_t gb = part.lo + gi * sp.gsz;
+    const uint32_t glen = min(sp.gsz, part.len - gi * sp.gsz);
     const uint64_t idx = wave_locate(ev, qs, gb, glen, r);
     next = adj[o + idx];
   }

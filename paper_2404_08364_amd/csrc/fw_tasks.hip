@@ -28,8 +28,10 @@ struct TaskEval {
   const uint32_t* __restrict__ w;
   uint64_t o;    // first weight of the task
   uint64_t end;  // n_tasks * size
+  uint64_t qa;   // quad run base (set by bind_quads)
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return w[o + i]; }
-  __device__ __forceinline__ void quad(uint64_t p, uint64_t out[4]) const {
+  __device__ __forceinline__ void quad(uint32_t q, uint64_t out[4]) const {
+    const uint64_t p = qa + 4ull * q;
     if (p + 4 <= end) {
       const uint4 v = *reinterpret_cast<const uint4*>(w + p);
       out[0] = v.x;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(256) void k_tasks(const uint32_t* __restrict__ w, u
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
   for (uint64_t j = wave; j < n_tasks; j += nwaves) {
-    TaskEval ev{w, j * size, n_tasks * size};
+    TaskEval ev{w, j * size, n_tasks * size, 0};
     int64_t pick;
     if (S == FW_TASK_ITS) {
       uint64_t blk[4];
@@ -201,7 +203,8 @@ int fw_sample_tasks(int sampler, const uint32_t* weights, uint64_t n_tasks, uint
   if (sampler < FW_TASK_ITS || sampler > FW_TASK_REJECTION)
     return fw::set_error(FW_EINVAL, "unknown task sampler");
   if (n_tasks == 0) return FW_OK;
-  if (size == 0) return fw::set_error(FW_EINVAL, "size must be > 0");
+  if (size == 0 || size >= fw::kMaxDegree)
+    return fw::set_error(FW_EINVAL, "size must be in 1 .. 2^28 - 1");
   if (!weights || !picks) return fw::set_error(FW_EINVAL, "weights or picks is NULL");
   if (n_tasks > (UINT64_MAX >> 2) / size) return fw::set_error(FW_EINVAL, "n_tasks * size too large");
   hipStream_t st = static_cast<hipStream_t>(stream);

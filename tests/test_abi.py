@@ -102,3 +102,8 @@ def test_sample_tasks_checks_arguments_on_host():
     assert lib.fw_sample_tasks(0, None, 0, 3, 1, None, None) == fw.OK
     assert lib.fw_sample_tasks(0, None, 4, 0, 1, None, None) == fw.EINVAL
     assert lib.fw_sample_tasks(0, None, 4, 3, 1, None, None) == fw.EINVAL
+
+
+def test_sample_tasks_size_limit():
+    from paper_2404_08364_amd import flowwalk as fw
+    assert fw.lib().fw_sample_tasks(0, None, 4, 1 << 28, 1, None, None) == fw.EINVAL
