@@ -253,7 +253,10 @@ struct Eval {
   uint32_t want;
   // First entry of the current slice's quad run (a multiple of 4): quad q
   // of the run holds the absolute entries qa + 4q .. qa + 4q + 3.
-  uint64_t qa;
+  uint64_t qa = 0;
+  // Weight times factor is exact as a 24-bit multiply (bound checked per
+  // launch on the host).
+  bool narrow = false;
 
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
     const uint64_t e = o + i;
@@ -295,14 +298,14 @@ struct Eval {
       const uint32_t u[4] = {a.x, a.y, a.z, a.w};
       bool in[4];
       mem.contains4(u, in);
-      // Blend arithmetically (mod 2^32, exact): selecting between struct
-      // members would let the compiler address the struct in scratch.
-      const uint32_t d_in = f_in - f_out, d_ret = f_ret - f_out;
+      // Factor selects between uniform copies (selecting struct members
+      // directly would let the compiler address the struct in scratch).
+      const uint32_t fo = f_out, fi = f_in, fr = f_ret;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool is_ret = u[j] == prev;
-        const uint32_t f = f_out + ((in[j] && !is_ret) ? d_in : 0u) + (is_ret ? d_ret : 0u);
-        out[j] = (uint64_t)wq[j] * f;
+        uint32_t f = in[j] ? fi : fo;
+        f = u[j] == prev ? fr : f;
+        out[j] = narrow ? (uint64_t)__umul24(wq[j], f) : (uint64_t)wq[j] * f;
       }
     } else if (ALGO == kMetaPath) {
       const uint32_t l = *reinterpret_cast<const uint32_t*>(

@@ -16,7 +16,19 @@ struct TuneCfg {
   uint32_t wgs_per_cu;  // persistent workgroups per CU
   uint32_t fetch;       // reserved (refills claim every empty slot at once)
   uint32_t hash_cells;  // LDS hash-set cells per workgroup (power of two)
+  uint32_t narrow;      // set per launch: max weight * max factor < 2^24, so a
+                        // weight times a factor is one 24-bit multiply
 };
+
+// max_w * max_f < 2^24: the product of a weight and a factor fits 32 bits
+// and 256 of them fit 32 bits.
+inline uint32_t narrow_products(uint64_t max_w, const DevParams& p) {
+  uint64_t f = p.f_ret;
+  if (p.f_in > f) f = p.f_in;
+  if (p.f_out > f) f = p.f_out;
+  if (f == 0) f = 1;
+  return (max_w < (1ull << 24) && f < (1ull << 24) && max_w * f < (1ull << 24)) ? 1u : 0u;
+}
 
 struct LaunchArgs {
   int algo;

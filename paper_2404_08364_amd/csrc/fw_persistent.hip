@@ -31,6 +31,12 @@ namespace fw {
 extern __shared__ __attribute__((aligned(16))) uint32_t fw_dyn_lds[];
 
 constexpr uint32_t kFib = 0x9E3779B1u;
+
+// Bucket of key u in a table of 2^(32 - shift) buckets (Fibonacci hashing:
+// the top bits of u times 2^32 / golden ratio).
+__device__ __forceinline__ uint32_t bucket_of(uint32_t u, uint32_t shift) {
+  return (u * kFib) >> shift;
+}
 constexpr int kGroups = 4;  // queries per wavefront
 constexpr int kGroupLanes = 16;
 constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
@@ -88,7 +94,7 @@ struct MemberAny {
       uint4 v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        b[j] = (u[j] * kFib) >> shift;
+        b[j] = bucket_of(u[j], shift);
         v[j] = bucket(b[j]);
       }
       bool more = false;
@@ -143,7 +149,7 @@ __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restric
   wave_sync_lds();
   for (uint64_t i = lane; i < tb.pd; i += kWave) {
     const uint32_t u = adj[tb.po + i];
-    uint32_t b = (u * kFib) >> tb.shift;
+    uint32_t b = bucket_of(u, tb.shift);
     for (;;) {
       uint32_t j = 0;
       for (; j < 4; ++j) {
@@ -264,13 +270,13 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
         wave_sync_lds();
       }
       if (global) row_contains4(ev.adj, tb.po, tb.pd, key, in);
-      const uint32_t d_in = ev.f_in - ev.f_out, d_ret = ev.f_ret - ev.f_out;
+      const uint32_t fo = ev.f_out, fi = ev.f_in, fr = ev.f_ret;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool is_ret = key[j] == ev.prev;
-        const uint32_t f = ev.f_out + ((in[j] && !is_ret) ? d_in : 0u) + (is_ret ? d_ret : 0u);
+        uint32_t f = in[j] ? fi : fo;
+        f = key[j] == ev.prev ? fr : f;
         const uint32_t wj = ((keep >> j) & 1u) ? wq[j] : 0u;
-        acc += (uint64_t)wj * f;
+        acc += ev.narrow ? (uint64_t)__umul24(wj, f) : (uint64_t)wj * f;
       }
     }
     const uint64_t tot = wave_sum(acc);
@@ -294,6 +300,8 @@ __device__ __forceinline__ Eval<ALGO, WEIGHTED, MEM> base_eval(const DevGraph& g
   ev.f_in = prm.f_in;
   ev.f_out = prm.f_out;
   ev.want = (ALGO == kMetaPath) ? schema_label(prm, t) : 0u;
+  ev.qa = 0;
+  ev.narrow = false;
   return ev;
 }
 
@@ -468,6 +476,7 @@ k_walk_persistent(
       }
       const uint64_t u = philox_draw(R.seed, R.qid_base + qid, t);
       auto ev = base_eval<ALGO, WEIGHTED, MemberAny>(g, prm, o, prev, t);
+      ev.narrow = cfg.narrow != 0;
       ev.mem.mode = tb.kind == 1 ? 1 : 0;
       ev.mem.base = tb.base;
       ev.mem.bmask = tb.bmask;

@@ -146,6 +146,7 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
 static int time_config(const fw_graph* g, LaunchArgs a, const TuneCfg& cfg, hipStream_t stream,
                        hipEvent_t e0, hipEvent_t e1, float* ms) {
   a.cfg = cfg;
+  a.cfg.narrow = narrow_products(g->max_w, a.prm);
   hipError_t e = launch_persistent(a, stream);  // warm-up
   if (e == hipSuccess) e = hipEventRecord(e0, stream);
   if (e == hipSuccess) e = launch_persistent(a, stream);

@@ -313,6 +313,7 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
     const bool staged = o.mode == FW_MODE_STAGED;
     rc = fw::resolve_tune(g, (int)algo, staged, o.tune, &a.cfg);
     if (rc) return rc;
+    a.cfg.narrow = fw::narrow_products(g->max_w, dp);
     e = fw::launch_persistent_checked(g, a, stream, o.use_graph != 0, staged);
   } else {
     return fail(FW_EINVAL, "unknown mode");

@@ -185,8 +185,11 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
                          hipMemcpyHostToDevice, b.stream);
     if (e != hipSuccess) return e;
     fw::ReqTable t{b.d_desc[a], b.d_prefix[a], k, total};
-    e = fw::launch_persistent_multi(a, dg, t, s->d_status, b.d_head + 16 * a, s->g->num_cus,
-                                    s->cfg[a], b.stream);
+    fw::TuneCfg cfg = s->cfg[a];
+    cfg.narrow = 1;
+    for (uint32_t i = 0; i < k; ++i) cfg.narrow &= fw::narrow_products(s->g->max_w, b.h_desc[a][i].prm);
+    e = fw::launch_persistent_multi(a, dg, t, s->d_status, b.d_head + 16 * a, s->g->num_cus, cfg,
+                                    b.stream);
     if (e != hipSuccess) return e;
   }
   for (auto& r : b.reqs) {

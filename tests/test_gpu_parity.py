@@ -85,6 +85,54 @@ def test_powerlaw_graph(env, powerlaw, mode, algo, factors, schema):
     _check(env, g, algo, factors, schema, starts, 12, 31337, mode)
 
 
+def _colliding_graph(npd, nother=150, V=6000, seed=1):
+    """Vertex 0 (prev) whose npd neighbours all fall into one bucket of the
+    persistent walker's LDS hash set (Fibonacci hashing, top bits of
+    u * 0x9E3779B1), so membership tests of vertex 1's neighbours must probe
+    long bucket chains; every walk goes 0 -> 1 -> ..."""
+    pd = npd + 1
+    bits = 2
+    while (1 << bits) < (2 * pd + 3) // 4:
+        bits += 1
+    shift = 32 - bits
+    h = lambda u: ((u * 0x9E3779B1) & 0xFFFFFFFF) >> shift  # noqa: E731
+    keys = [u for u in range(2, V) if h(u) == h(2)][:npd]
+    rng = np.random.default_rng(seed)
+    ks = set(keys)
+    others = [u for u in rng.permutation(np.arange(2, V)).tolist() if u not in ks][:nother]
+    edges = [(0, 1, 1_000_000, 0)] + [(0, k, 1, 0) for k in keys]
+    edges += [(1, k, 1 + k % 7, 0) for k in keys] + [(1, o, 1 + o % 5, 0) for o in others]
+    edges += [(i, i + 1, 1, 0) for i in range(2, V - 1)]
+    return csr_from_edges(V, sorted(set(edges)))
+
+
+@pytest.mark.parametrize("npd", [30, 60, 120])
+def test_hash_bucket_collisions(env, npd):
+    torch, fw = env
+    g = _colliding_graph(npd)
+    starts = np.zeros(5000, dtype=np.uint32)
+    for tune in [dict(hash_cells=1024, wgs_per_cu=8, tiny_max=0),
+                 dict(hash_cells=256, wgs_per_cu=4, tiny_max=16)]:
+        _check(env, g, "node2vec", (1, 2, 4), (), starts, 3, 777, "persistent",
+               tune=fw.make_tune(**tune))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("factors", [(1, 2, 4), (7, 3, 5), (1, 1, 16)])
+@pytest.mark.parametrize("wmax", [(1 << 24) // 16 - 1, (1 << 24) // 16, (1 << 31) + 12345])
+def test_node2vec_weight_widths(env, mode, factors, wmax):
+    """Weight times factor just below, at and far above 2^24: the walkers
+    switch between 24-bit and full products at that bound, and both must
+    give the oracle's walks."""
+    g = synth.chung_lu(6_000, 90_000, 2.1, 1.5, seed=17)
+    rng = np.random.default_rng(wmax % 1000)
+    w = rng.integers(1, wmax + 1, g.n_edges, dtype=np.uint64)
+    w[rng.integers(0, g.n_edges, 50)] = wmax
+    g.weights = w.astype(np.uint32)
+    starts = np.arange(g.n_vertices, dtype=np.uint32)[::3]
+    _check(env, g, "node2vec", factors, (), starts, 9, 5151, mode)
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("weighted", [True, False])
 @pytest.mark.parametrize("stop", [(1, 5), (0, 1), (1, 1), (2, 3)])
