@@ -305,7 +305,8 @@ struct Eval {
       for (int j = 0; j < 4; ++j) {
         uint32_t f = in[j] ? fi : fo;
         f = u[j] == prev ? fr : f;
-        out[j] = narrow ? (uint64_t)__umul24(wq[j], f) : (uint64_t)wq[j] * f;
+        // (HIP's __umul24 returns a signed int: go through uint32_t.)
+        out[j] = narrow ? (uint64_t)(uint32_t)__umul24(wq[j], f) : (uint64_t)wq[j] * f;
       }
     } else if (ALGO == kMetaPath) {
       const uint32_t l = *reinterpret_cast<const uint32_t*>(

@@ -276,7 +276,7 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
         uint32_t f = in[j] ? fi : fo;
         f = key[j] == ev.prev ? fr : f;
         const uint32_t wj = ((keep >> j) & 1u) ? wq[j] : 0u;
-        acc += ev.narrow ? (uint64_t)__umul24(wj, f) : (uint64_t)wj * f;
+        acc += ev.narrow ? (uint64_t)(uint32_t)__umul24(wj, f) : (uint64_t)wj * f;
       }
     }
     const uint64_t tot = wave_sum(acc);

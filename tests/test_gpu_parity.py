@@ -88,8 +88,8 @@ def test_powerlaw_graph(env, powerlaw, mode, algo, factors, schema):
 def _colliding_graph(npd, nother=150, V=6000, seed=1):
     """Vertex 0 (prev) whose npd neighbours all fall into one bucket of the
     persistent walker's LDS hash set (Fibonacci hashing, top bits of
-    u * 0x9E3779B1), so membership tests of vertex 1's neighbours must probe
-    long bucket chains; every walk goes 0 -> 1 -> ..."""
+    u * 0x9E3779B1 mod 2^32), so membership tests of vertex 1's neighbours
+    must probe long bucket chains; every walk goes 0 -> 1 -> ..."""
     pd = npd + 1
     bits = 2
     while (1 << bits) < (2 * pd + 3) // 4:
@@ -106,10 +106,11 @@ def _colliding_graph(npd, nother=150, V=6000, seed=1):
     return csr_from_edges(V, sorted(set(edges)))
 
 
-@pytest.mark.parametrize("npd", [30, 60, 120])
-def test_hash_bucket_collisions(env, npd):
+@pytest.mark.parametrize("npd,V", [(30, 6000), (60, 6000), (120, 6000), (300, 120_000)])
+def test_hash_bucket_collisions(env, npd, V):
+    """Tables of 16 to 256 buckets with one bucket chain holding every key."""
     torch, fw = env
-    g = _colliding_graph(npd)
+    g = _colliding_graph(npd, V=V)
     starts = np.zeros(5000, dtype=np.uint32)
     for tune in [dict(hash_cells=1024, wgs_per_cu=8, tiny_max=0),
                  dict(hash_cells=256, wgs_per_cu=4, tiny_max=16)]:
