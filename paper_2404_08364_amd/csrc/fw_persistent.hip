@@ -164,51 +164,83 @@ __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restric
   tb.kind = 1;
 }
 
+using lds_ptr = const __attribute__((address_space(3))) uint32_t*;
+
+// One halving step of lds_search4: the lower bound of u[j] is in
+// [p[j], p[j] + 2h] before and in [p[j], p[j] + h] after.
+__device__ __forceinline__ void lds_step4(lds_ptr p[4], const uint32_t u[4], uint32_t h) {
+  uint32_t x[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] = p[j][h - 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) p[j] = (x[j] < u[j]) ? p[j] + h : p[j];
+}
+
 // Four lower-bound searches in the sorted LDS run fw_dyn_lds[b, b + n), one
-// trip count for all lanes (n is wave-uniform).
-__device__ __forceinline__ void lds_contains4(uint32_t b, uint32_t n, const uint32_t u[4],
-                                              bool hit[4]) {
+// trip count for all lanes (n is wave-uniform): lb[j] is the number of
+// entries below u[j], hit[j] whether u[j] occurs in the run.  With P the
+// largest power of two not above n, one probe at n - P - 1 leaves a range of
+// P + 1 candidates, which halving steps narrow to two; the last five steps
+// (h = 16 .. 1) are unrolled and entered by a switch, so their probe offsets
+// and increments are immediates (4h <= 64 is an inline constant).
+__device__ __forceinline__ void lds_search4(uint32_t b, uint32_t n, const uint32_t u[4],
+                                            uint32_t lb[4], bool hit[4]) {
   if (n == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) hit[j] = false;
+    for (int j = 0; j < 4; ++j) {
+      lb[j] = 0;
+      hit[j] = false;
+    }
     return;
   }
-  uint32_t base[4] = {b, b, b, b};
-  uint32_t len = n;
-  while (len > 1) {
-    const uint32_t half = len >> 1;
-    uint32_t x[4];
+  const lds_ptr run = (lds_ptr)(fw_dyn_lds + b);
+  const uint32_t lg = 31u - (uint32_t)__builtin_clz(n);
+  const uint32_t P = 1u << lg;
+  lds_ptr p[4] = {run, run, run, run};
+  if (n > P) {
+    const uint32_t x = run[n - P - 1];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = fw_dyn_lds[base[j] + half];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) base[j] = (x[j] < u[j]) ? base[j] + half : base[j];
-    len -= half;
+    for (int j = 0; j < 4; ++j) p[j] = (x < u[j]) ? run + (n - P) : run;
   }
-  const uint32_t last = b + n - 1;
+  for (uint32_t h = P >> 1; h >= 32; h >>= 1) lds_step4(p, u, h);
+  switch (lg < 5 ? lg : 5) {
+    case 5: lds_step4(p, u, 16); [[fallthrough]];
+    case 4: lds_step4(p, u, 8); [[fallthrough]];
+    case 3: lds_step4(p, u, 4); [[fallthrough]];
+    case 2: lds_step4(p, u, 2); [[fallthrough]];
+    case 1: lds_step4(p, u, 1); [[fallthrough]];
+    default: break;
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t x0 = fw_dyn_lds[base[j]];
-    const uint32_t x1 = fw_dyn_lds[min(base[j] + 1, last)];
-    hit[j] = (x0 == u[j]) || (x0 < u[j] && base[j] < last && x1 == u[j]);
+    const uint32_t i = (uint32_t)(p[j] - run);  // the lower bound is i or i + 1
+    const uint32_t x0 = run[i];
+    const uint32_t x1 = run[min(i + 1, n - 1)];
+    const bool lt = x0 < u[j];
+    lb[j] = i + (lt ? 1u : 0u);
+    hit[j] = (x0 == u[j]) | (lt & (i + 1 < n) & (x1 == u[j]));
   }
 }
 
 // Pass 1 of a node2vec hop by merging the sorted rows N(cur) and N(prev).
 // Each iteration takes one 64-quad chunk (256 consecutive entries of N(cur),
-// ascending): it stages into LDS the entries of N(prev) from a cursor up to
-// the chunk's largest key, 256 per round, and tests the chunk's keys against
-// that window.  Entries below the largest key cannot match any later key, so
-// the cursor moves past them; a window too large for the region falls back
-// to binary search in global memory for that chunk and for the rest of the
-// pass.  Lane g returns the total of group g (the layout of GroupSplit).
+// ascending; its largest key kmax is its last entry).  The entries of N(prev)
+// from a cursor up to kmax are staged into LDS, 256 per round with lane-
+// consecutive loads, and the chunk's keys are looked up there by binary
+// search.  A run too long for the region is taken in region-sized
+// sub-windows whose lookups are or-ed.  Entries below kmax cannot match a
+// later key, so the cursor then moves past them (their count is the sum of
+// kmax's lower bounds in the sub-windows).  Lane g returns the total of group g (the layout of
+// GroupSplit).
 template <class E>
 __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSlice& s,
                                                        const GroupSplit& sp, const Table& tb,
                                                        int lane) {
   const char* __restrict__ wrun = reinterpret_cast<const char*>(ev.w + s.a);
   const char* __restrict__ arun = reinterpret_cast<const char*>(ev.adj + s.a);
-  uint64_t cursor = 0;
-  bool global = false;
+  const uint32_t* __restrict__ prow = ev.adj + tb.po;  // N(prev)
+  const uint32_t jend = (s.lead + s.d - 1) & 3u;      // slice's last entry in its quad
+  uint64_t cursor = 0;  // entries of N(prev) below every key still to come
   uint64_t mine = 0;
   for (uint32_t g = 0; g < sp.groups; ++g) {
     const uint32_t gb = g * sp.gsz;
@@ -231,45 +263,60 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
       }
       const uint4 a = *reinterpret_cast<const uint4*>(arun + qq * 16u);
       const uint32_t key[4] = {a.x, a.y, a.z, a.w};
-      uint32_t kmax = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) kmax = ((keep >> j) & 1u) ? max(kmax, key[j]) : kmax;
-      kmax = wave_max32(kmax);
+      // The chunk's last entry: entry jl of the quad in lane L (uniform).
+      const uint32_t L = min((uint32_t)kWave, ge - c0) - 1;
+      const uint32_t jl = (c0 + L + 1 == s.nq) ? jend : 3u;
+      const uint32_t kmax = readlane32(jl == 0 ? key[0] : jl == 1 ? key[1] : jl == 2 ? key[2] : key[3],
+                                       (int)L);
       bool in[4] = {false, false, false, false};
-      if (!global) {
-        // Stage N(prev)[cursor, cursor + W): the entries <= kmax (a prefix,
-        // N(prev) being sorted).
-        const uint32_t* __restrict__ pr = ev.adj + tb.po + cursor;
-        const uint64_t left = tb.pd - cursor;  // entries of N(prev) from the cursor
-        uint32_t W = 0, below = 0;              // staged entries <= kmax / < kmax
-        for (;;) {
-          if (W + 4 * kWave > tb.cells) {  // window larger than the region
-            global = true;
-            break;
-          }
-          uint32_t cnt_le = 0, cnt_lt = 0;
+      uint64_t sub = cursor;  // first entry of the current sub-window
+      uint64_t below = 0;     // entries below kmax in the sub-windows so far
+      for (;;) {
+        // Stage N(prev)[sub, sub + W): the entries <= kmax (a prefix, N(prev)
+        // being sorted), or as many full rounds of them as the region holds.
+        const uint32_t* __restrict__ pr = prow + sub;
+        // Entries left in N(prev) (clamped: a region holds far fewer).
+        const uint32_t left = (uint32_t)min(tb.pd - sub, (uint64_t)0xFFFFFFFFu);
+        uint32_t W = 0;
+        bool more = false;  // the region filled up before the run ended
+        if (left != 0) {
+          for (;;) {
+            if (W + 4 * kWave > tb.cells) {
+              more = true;
+              break;
+            }
+            // All four loads first, then the stores and counts (kEnd, past
+            // the row, is above every key).
+            uint32_t v[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const uint32_t k = W + 4 * lane + j;
-            const bool in_row = k < left;
-            const uint32_t v = in_row ? pr[k] : kEnd;
-            cnt_le += (in_row && v <= kmax) ? 1u : 0u;
-            cnt_lt += (in_row && v < kmax) ? 1u : 0u;
-            fw_dyn_lds[tb.base + k] = v;
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t k = W + (uint32_t)j * kWave + (uint32_t)lane;
+              v[j] = pr[k < left ? k : 0u];
+            }
+            uint32_t n_le = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t k = W + (uint32_t)j * kWave + (uint32_t)lane;
+              const uint32_t x = k < left ? v[j] : kEnd;
+              fw_dyn_lds[tb.base + k] = x;
+              n_le += (uint32_t)__builtin_popcountll(ballot(x <= kmax));
+            }
+            W += n_le;
+            if (n_le < 4 * kWave) break;
           }
-          const uint32_t n_le = wave_sum32(cnt_le);
-          below += wave_sum32(cnt_lt);
-          W += n_le;
-          if (n_le < 4 * kWave) break;
         }
         wave_sync_lds();
-        if (!global) {
-          lds_contains4(tb.base, W, key, in);
-          cursor += below;
-        }
+        uint32_t lb[4];
+        bool h[4];
+        lds_search4(tb.base, W, key, lb, h);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) in[j] |= h[j];
+        below += readlane32(jl == 0 ? lb[0] : jl == 1 ? lb[1] : jl == 2 ? lb[2] : lb[3], (int)L);
         wave_sync_lds();
+        if (!more) break;
+        sub += W;
       }
-      if (global) row_contains4(ev.adj, tb.po, tb.pd, key, in);
+      cursor += below;
       const uint32_t fo = ev.f_out, fi = ev.f_in, fr = ev.f_ret;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {

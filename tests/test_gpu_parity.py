@@ -118,6 +118,38 @@ def test_hash_bucket_collisions(env, npd, V):
                tune=fw.make_tune(**tune))
 
 
+def _window_graph(n_prev, prev_step, n_cur, cur_step, V=40_000, dup_every=37):
+    """Vertex 0 (prev) and vertex 1 (cur) with neighbours spread over the same
+    id range at different densities, parallel edges in both rows, and a
+    heavy edge 0 -> 1, so most walks from 0 take the hop 1 -> ? with prev 0.
+    A dense N(prev) gives the merge of sorted rows windows far longer than the
+    LDS region (taken in sub-windows); a sparse one gives short windows."""
+    prev = [2 + prev_step * i for i in range(n_prev)]
+    cur = [2 + cur_step * i for i in range(n_cur)]
+    edges = [(0, 1, 1_000_000, 0)]
+    edges += [(0, k, 1 + k % 3, 0) for k in prev] + [(0, k, 5, 0) for k in prev[::dup_every]]
+    edges += [(1, k, 1 + k % 7, 0) for k in cur] + [(1, k, 9, 0) for k in cur[::dup_every]]
+    edges += [(i, i + 1, 1, 0) for i in range(2, V - 1)]
+    return csr_from_edges(V, sorted(set(edges)), symmetric=False)
+
+
+@pytest.mark.parametrize("shape", [(2000, 1, 400, 7), (3000, 1, 2000, 1), (600, 7, 4200, 1),
+                                   (1500, 3, 1100, 5)])
+def test_merge_windows(env, shape):
+    """node2vec hops whose N(prev) is too large for the LDS hash set: merge
+    windows shorter than a staging round, and longer than the whole region."""
+    torch, fw = env
+    g = _window_graph(*shape)
+    starts = np.zeros(3000, dtype=np.uint32)
+    for tune in [dict(hash_cells=1024, wgs_per_cu=8, tiny_max=16),
+                 dict(hash_cells=512, wgs_per_cu=8, tiny_max=0),
+                 dict(hash_cells=256, wgs_per_cu=4, tiny_max=16)]:
+        _check(env, g, "node2vec", (1, 2, 4), (), starts, 4, 4242, "persistent",
+               tune=fw.make_tune(**tune))
+    for mode in ("plain", "staged"):
+        _check(env, g, "node2vec", (1, 2, 4), (), starts, 4, 4242, mode)
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("factors", [(1, 2, 4), (7, 3, 5), (1, 1, 16)])
 @pytest.mark.parametrize("wmax", [(1 << 24) // 16 - 1, (1 << 24) // 16, (1 << 31) + 12345])
