@@ -173,18 +173,26 @@ __device__ __forceinline__ int first_lane(uint64_t mask) { return (int)__builtin
 // Transition weights (section 2.1).  One evaluator per hop; element i is the
 // i-th neighbour of the current vertex in CSR order.
 // ---------------------------------------------------------------------------
+// Entry i of a row, addressed by a 32-bit byte offset from the row's start
+// (rows are shorter than 2^28 entries; with a wave-uniform row this is one
+// load with a scalar base and no 64-bit address arithmetic).
+__device__ __forceinline__ uint32_t row_at(const uint32_t* __restrict__ row, uint32_t i) {
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(row) + i * 4u);
+}
+
 // Lower-bound search of u in the sorted row adj[b, b + n).
 __device__ __forceinline__ bool row_contains(const uint32_t* __restrict__ adj, uint64_t b,
                                              uint64_t n, uint32_t u) {
-  uint64_t lo = b, hi = b + n;
+  const uint32_t* __restrict__ row = adj + b;
+  uint32_t lo = 0, hi = (uint32_t)n;
   while (lo < hi) {
-    const uint64_t mid = lo + ((hi - lo) >> 1);
-    if (adj[mid] < u)
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (row_at(row, mid) < u)
       lo = mid + 1;
     else
       hi = mid;
   }
-  return lo < b + n && adj[lo] == u;
+  return lo < (uint32_t)n && row_at(row, lo) == u;
 }
 
 // Label of schema entry t mod schema_len, without dynamic register indexing
@@ -199,7 +207,8 @@ __device__ __forceinline__ uint32_t schema_label(const DevParams& p, uint32_t t)
 
 // Four lower-bound searches in the sorted row adj[b, b + n) with one trip
 // count for all of them (n is wave-uniform at the callers): no divergence,
-// and the four probes of a step are issued together.
+// and the four probes of a step, and the two reads of the last step, are
+// issued together.
 __device__ __forceinline__ void row_contains4(const uint32_t* __restrict__ adj, uint64_t b,
                                               uint64_t n, const uint32_t u[4], bool hit[4]) {
   if (n == 0) {
@@ -207,23 +216,25 @@ __device__ __forceinline__ void row_contains4(const uint32_t* __restrict__ adj, 
     for (int j = 0; j < 4; ++j) hit[j] = false;
     return;
   }
-  uint64_t base[4] = {b, b, b, b};
-  uint64_t len = n;
+  const uint32_t* __restrict__ row = adj + b;
+  const uint32_t n32 = (uint32_t)n;  // rows are shorter than 2^28
+  uint32_t base[4] = {0, 0, 0, 0};
+  uint32_t len = n32;
   while (len > 1) {  // invariant: the lower bound of u[j] is in [base[j], base[j] + len]
-    const uint64_t half = len >> 1;
+    const uint32_t half = len >> 1;
     uint32_t x[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = adj[base[j] + half];
+    for (int j = 0; j < 4; ++j) x[j] = row_at(row, base[j] + half);
 #pragma unroll
     for (int j = 0; j < 4; ++j) base[j] = (x[j] < u[j]) ? base[j] + half : base[j];
     len -= half;
   }
-  const uint64_t last = b + n - 1;
+  const uint32_t last = n32 - 1;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t x0 = adj[base[j]];
-    const uint32_t x1 = adj[min(base[j] + 1, last)];
-    hit[j] = (x0 == u[j]) || (x0 < u[j] && base[j] < last && x1 == u[j]);
+    const uint32_t x0 = row_at(row, base[j]);
+    const uint32_t x1 = row_at(row, min(base[j] + 1, last));
+    hit[j] = (x0 == u[j]) | ((x0 < u[j]) & (base[j] < last) & (x1 == u[j]));
   }
 }
 

@@ -16,7 +16,7 @@
 //
 // Node2vec membership in N(prev) for non-tiny hops uses the wavefront's LDS
 // region: an exact 4-cell-bucket hash set of N(prev) when it fits; otherwise,
-// while N(prev) is at most 8x N(cur), a merge of the two sorted rows (each
+// while N(prev) is at most 16x N(cur), a merge of the two sorted rows (each
 // 256-entry chunk of N(cur) stages the window of N(prev) that holds its value
 // range into LDS and searches it there); when N(prev) is much larger than
 // N(cur), binary search of the sorted row in global memory.  No global memory
@@ -61,7 +61,7 @@ __device__ __forceinline__ bool has4(uint4 v, uint32_t u) {
 //      in the first bucket, in probe order from its hash, that had a free cell
 //      when it was inserted, so a lookup stops at a hit or at a bucket with a
 //      free cell.
-// (Mode 2, the merge of sorted rows, has its own pass: merge_group_totals.)
+// (Mode 2, the merge of sorted rows, has its own code: merge_chunk.)
 // One type for all modes keeps a single copy of the sampler in the kernel.
 struct MemberAny {
   int mode;
@@ -133,7 +133,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restrict__ adj,
                                             uint64_t d, int lane) {
   tb.kind = 0;
-  if (tb.pd == 0 || tb.pd > 8 * d) return;  // a few searches beat a build
+  // Past 16x, searching for the few keys reads less than the build or the
+  // merge (16 against 8, 32 and 64 measured on R-MAT-22 node2vec).
+  if (tb.pd == 0 || tb.pd > 16 * d) return;
   if (2 * tb.pd > tb.cells) {
     // Too large for the hash set: merge the sorted rows (the region must
     // hold at least one 256-entry staging round).
@@ -222,109 +224,133 @@ __device__ __forceinline__ void lds_search4(uint32_t b, uint32_t n, const uint32
   }
 }
 
-// Pass 1 of a node2vec hop by merging the sorted rows N(cur) and N(prev).
-// Each iteration takes one 64-quad chunk (256 consecutive entries of N(cur),
-// ascending; its largest key kmax is its last entry).  The entries of N(prev)
-// from a cursor up to kmax are staged into LDS, 256 per round with lane-
-// consecutive loads, and the chunk's keys are looked up there by binary
-// search.  A run too long for the region is taken in region-sized
-// sub-windows whose lookups are or-ed.  Entries below kmax cannot match a
-// later key, so the cursor then moves past them (their count is the sum of
-// kmax's lower bounds in the sub-windows).  Lane g returns the total of group g (the layout of
-// GroupSplit).
+// One 64-quad chunk of a node2vec hop by merging the sorted rows N(cur) and
+// N(prev): quads [c0, min(c0 + 64, ge)) of the slice, lane i taking quad
+// c0 + i (256 consecutive entries of N(cur), ascending; the chunk's largest
+// key kmax is its last entry).  The entries of N(prev) from `cursor` up to
+// kmax are staged into LDS (a first round of 64 entries, then rounds of 256
+// while they come back full, with lane-consecutive loads) and the chunk's
+// keys are looked up there by binary search.  A run too long for the region
+// is taken in region-sized sub-windows whose lookups are or-ed.  Entries
+// below kmax cannot match a later key, so the cursor then moves past them
+// (their count is the sum of kmax's lower bounds in the sub-windows).  out[j]
+// is the transition weight of entry j of the lane's quad (0 outside the
+// slice or the chunk).
 template <class E>
-__device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSlice& s,
-                                                       const GroupSplit& sp, const Table& tb,
-                                                       int lane) {
+__device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, const Table& tb,
+                                            uint32_t c0, uint32_t ge, uint64_t& cursor,
+                                            int lane, uint64_t out[4]) {
   const char* __restrict__ wrun = reinterpret_cast<const char*>(ev.w + s.a);
   const char* __restrict__ arun = reinterpret_cast<const char*>(ev.adj + s.a);
   const uint32_t* __restrict__ prow = ev.adj + tb.po;  // N(prev)
   const uint32_t jend = (s.lead + s.d - 1) & 3u;      // slice's last entry in its quad
+  const uint32_t q = c0 + lane;
+  const bool valid = q < ge;
+  const uint32_t qq = valid ? q : c0;
+  uint32_t keep = valid ? 0xFu : 0u;
+  if (valid && (qq == 0 || qq + 1 == s.nq)) {
+    keep = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) keep |= s.inside(qq, j) ? (1u << j) : 0u;
+  }
+  uint32_t wq[4] = {1u, 1u, 1u, 1u};
+  if (ev.w != nullptr) {
+    const uint4 v = *reinterpret_cast<const uint4*>(wrun + qq * 16u);
+    wq[0] = v.x; wq[1] = v.y; wq[2] = v.z; wq[3] = v.w;
+  }
+  const uint4 a = *reinterpret_cast<const uint4*>(arun + qq * 16u);
+  const uint32_t key[4] = {a.x, a.y, a.z, a.w};
+  // The chunk's last entry: entry jl of the quad in lane L (uniform).
+  const uint32_t L = min((uint32_t)kWave, ge - c0) - 1;
+  const uint32_t jl = (c0 + L + 1 == s.nq) ? jend : 3u;
+  const uint32_t kmax = readlane32(jl == 0 ? key[0] : jl == 1 ? key[1] : jl == 2 ? key[2] : key[3],
+                                   (int)L);
+  bool in[4] = {false, false, false, false};
+  uint64_t sub = cursor;  // first entry of the current sub-window
+  uint64_t below = 0;     // entries below kmax in the sub-windows so far
+  for (;;) {
+    // Stage N(prev)[sub, sub + W): the entries <= kmax (a prefix, N(prev)
+    // being sorted), or as many full rounds of them as the region holds.
+    const uint32_t* __restrict__ pr = prow + sub;
+    // Entries left in N(prev) (clamped: a region holds far fewer).
+    const uint32_t left = (uint32_t)min(tb.pd - sub, (uint64_t)0xFFFFFFFFu);
+    uint32_t W = 0;
+    bool more = false;  // the region filled up before the run ended
+    if (left != 0) {
+      // Most windows are short: a first round of 64 entries, then
+      // rounds of 256 while they come back full.
+      const uint32_t k0 = (uint32_t)lane;
+      const uint32_t v0 = pr[k0 < left ? k0 : 0u];
+      const uint32_t x0 = k0 < left ? v0 : kEnd;  // kEnd is above every key
+      fw_dyn_lds[tb.base + k0] = x0;
+      W = (uint32_t)__builtin_popcountll(ballot(x0 <= kmax));
+      bool full = W == (uint32_t)kWave;
+      while (full) {
+        if (W + 4 * kWave > tb.cells) {
+          more = true;
+          break;
+        }
+        // All four loads first, then the stores and counts.
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t k = W + (uint32_t)j * kWave + (uint32_t)lane;
+          v[j] = pr[k < left ? k : 0u];
+        }
+        uint32_t n_le = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t k = W + (uint32_t)j * kWave + (uint32_t)lane;
+          const uint32_t x = k < left ? v[j] : kEnd;
+          fw_dyn_lds[tb.base + k] = x;
+          n_le += (uint32_t)__builtin_popcountll(ballot(x <= kmax));
+        }
+        W += n_le;
+        full = n_le == 4u * kWave;
+      }
+    }
+    wave_sync_lds();
+    uint32_t lb[4];
+    bool h[4];
+    lds_search4(tb.base, W, key, lb, h);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) in[j] |= h[j];
+    below += readlane32(jl == 0 ? lb[0] : jl == 1 ? lb[1] : jl == 2 ? lb[2] : lb[3], (int)L);
+    wave_sync_lds();
+    if (!more) break;
+    sub += W;
+  }
+  cursor += below;
+  const uint32_t fo = ev.f_out, fi = ev.f_in, fr = ev.f_ret;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t f = in[j] ? fi : fo;
+    f = key[j] == ev.prev ? fr : f;
+    const uint32_t wj = ((keep >> j) & 1u) ? wq[j] : 0u;
+    out[j] = ev.narrow ? (uint64_t)(uint32_t)__umul24(wj, f) : (uint64_t)wj * f;
+  }
+}
+
+// Pass 1 of a node2vec hop by merging the sorted rows, one chunk after the
+// other with a cursor into N(prev) that only moves forward.  Lane g returns
+// the total of group g (the layout of GroupSplit) and in gcur the cursor at
+// the start of group g, from which the group can be merged again.
+template <class E>
+__device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSlice& s,
+                                                       const GroupSplit& sp, const Table& tb,
+                                                       int lane, uint64_t& gcur) {
   uint64_t cursor = 0;  // entries of N(prev) below every key still to come
   uint64_t mine = 0;
+  gcur = 0;
   for (uint32_t g = 0; g < sp.groups; ++g) {
     const uint32_t gb = g * sp.gsz;
     const uint32_t ge = min(gb + sp.gsz, s.nq);
+    if ((uint32_t)lane == g) gcur = cursor;
     uint64_t acc = 0;
     for (uint32_t c0 = gb; c0 < ge; c0 += kWave) {
-      const uint32_t q = c0 + lane;
-      const bool valid = q < ge;
-      const uint32_t qq = valid ? q : c0;
-      uint32_t keep = valid ? 0xFu : 0u;
-      if (valid && (qq == 0 || qq + 1 == s.nq)) {
-        keep = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) keep |= s.inside(qq, j) ? (1u << j) : 0u;
-      }
-      uint32_t wq[4] = {1u, 1u, 1u, 1u};
-      if (ev.w != nullptr) {
-        const uint4 v = *reinterpret_cast<const uint4*>(wrun + qq * 16u);
-        wq[0] = v.x; wq[1] = v.y; wq[2] = v.z; wq[3] = v.w;
-      }
-      const uint4 a = *reinterpret_cast<const uint4*>(arun + qq * 16u);
-      const uint32_t key[4] = {a.x, a.y, a.z, a.w};
-      // The chunk's last entry: entry jl of the quad in lane L (uniform).
-      const uint32_t L = min((uint32_t)kWave, ge - c0) - 1;
-      const uint32_t jl = (c0 + L + 1 == s.nq) ? jend : 3u;
-      const uint32_t kmax = readlane32(jl == 0 ? key[0] : jl == 1 ? key[1] : jl == 2 ? key[2] : key[3],
-                                       (int)L);
-      bool in[4] = {false, false, false, false};
-      uint64_t sub = cursor;  // first entry of the current sub-window
-      uint64_t below = 0;     // entries below kmax in the sub-windows so far
-      for (;;) {
-        // Stage N(prev)[sub, sub + W): the entries <= kmax (a prefix, N(prev)
-        // being sorted), or as many full rounds of them as the region holds.
-        const uint32_t* __restrict__ pr = prow + sub;
-        // Entries left in N(prev) (clamped: a region holds far fewer).
-        const uint32_t left = (uint32_t)min(tb.pd - sub, (uint64_t)0xFFFFFFFFu);
-        uint32_t W = 0;
-        bool more = false;  // the region filled up before the run ended
-        if (left != 0) {
-          for (;;) {
-            if (W + 4 * kWave > tb.cells) {
-              more = true;
-              break;
-            }
-            // All four loads first, then the stores and counts (kEnd, past
-            // the row, is above every key).
-            uint32_t v[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const uint32_t k = W + (uint32_t)j * kWave + (uint32_t)lane;
-              v[j] = pr[k < left ? k : 0u];
-            }
-            uint32_t n_le = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const uint32_t k = W + (uint32_t)j * kWave + (uint32_t)lane;
-              const uint32_t x = k < left ? v[j] : kEnd;
-              fw_dyn_lds[tb.base + k] = x;
-              n_le += (uint32_t)__builtin_popcountll(ballot(x <= kmax));
-            }
-            W += n_le;
-            if (n_le < 4 * kWave) break;
-          }
-        }
-        wave_sync_lds();
-        uint32_t lb[4];
-        bool h[4];
-        lds_search4(tb.base, W, key, lb, h);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) in[j] |= h[j];
-        below += readlane32(jl == 0 ? lb[0] : jl == 1 ? lb[1] : jl == 2 ? lb[2] : lb[3], (int)L);
-        wave_sync_lds();
-        if (!more) break;
-        sub += W;
-      }
-      cursor += below;
-      const uint32_t fo = ev.f_out, fi = ev.f_in, fr = ev.f_ret;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        uint32_t f = in[j] ? fi : fo;
-        f = key[j] == ev.prev ? fr : f;
-        const uint32_t wj = ((keep >> j) & 1u) ? wq[j] : 0u;
-        acc += ev.narrow ? (uint64_t)(uint32_t)__umul24(wj, f) : (uint64_t)wj * f;
-      }
+      uint64_t w[4];
+      merge_chunk(ev, s, tb, c0, ge, cursor, lane, w);
+      acc += (w[0] + w[1]) + (w[2] + w[3]);
     }
     const uint64_t tot = wave_sum(acc);
     if ((uint32_t)lane == g) mine = tot;
@@ -536,7 +562,8 @@ k_walk_persistent(
         // Pass 1 by merge; the locate re-evaluates one group with searches.
         const QuadSlice qs(o, d);
         const GroupSplit sp(qs.nq);
-        const uint64_t mine = merge_group_totals(ev, qs, sp, tb, lane);
+        uint64_t gcur;
+        const uint64_t mine = merge_group_totals(ev, qs, sp, tb, lane, gcur);
         const uint64_t incl = wave_incl_scan(mine);
         const uint64_t total = readlane64(incl, kWave - 1);
         idx = -1;
@@ -546,7 +573,17 @@ k_walk_persistent(
           const int gs = m ? first_lane(m) : (int)sp.groups - 1;
           r -= readlane64(incl - mine, gs);
           const uint32_t lo = (uint32_t)gs * sp.gsz;
-          idx = (int64_t)wave_locate(ev, qs, lo, min(sp.gsz, qs.nq - lo), r);
+          const uint32_t len = min(sp.gsz, qs.nq - lo);
+          if (len <= (uint32_t)kWave) {
+            // A one-chunk group (rows up to 16,384 entries): merge it again
+            // from its cursor and pick inside it.
+            uint64_t cur = readlane64(gcur, gs);
+            uint64_t w[4];
+            merge_chunk(ev, qs, tb, lo, lo + len, cur, lane, w);
+            idx = pick_in_quads(w, qs, lo, len, r, true, 0);
+          } else {
+            idx = (int64_t)wave_locate(ev, qs, lo, len, r);
+          }
         }
       } else {
         idx = wave_pick(ev, o, d, u);

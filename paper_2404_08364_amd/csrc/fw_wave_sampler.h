@@ -98,6 +98,28 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
   return mine;
 }
 
+// Last level: lane i holds the weights of quad lo + i (0 for i >= len,
+// len <= 64).  With have_r the draw r is below their total; otherwise
+// r = floor(u * T / 2^64) from the total T.  Returns the picked index
+// relative to s.o, or -1 when the total is 0.
+__device__ __forceinline__ int64_t pick_in_quads(const uint64_t w[4], const QuadSlice& s,
+                                                 uint32_t lo, uint32_t len, uint64_t r,
+                                                 bool have_r, uint64_t u) {
+  const uint64_t c0 = w[0], c1 = c0 + w[1], c2 = c1 + w[2], tot = c2 + w[3];
+  const uint64_t incl = wave_incl_scan(tot);
+  if (!have_r) {
+    const uint64_t total = readlane64(incl, kWave - 1);
+    if (total == 0) return -1;
+    r = scale_draw(u, total);
+  }
+  const uint64_t m = ballot(incl > r);
+  const int L = m ? first_lane(m) : (int)(len ? len : 1) - 1;
+  const uint64_t rr = r - (incl - tot);  // meaningful in lane L
+  const uint32_t j = rr < c0 ? 0u : rr < c1 ? 1u : rr < c2 ? 2u : 3u;
+  const uint32_t jl = readlane32(j, L);
+  return (int64_t)(4 * (lo + (uint32_t)L) + jl) - (int64_t)s.lead;
+}
+
 // Descends from quads [lo, lo + len) to the picked entry.  With have_r the
 // draw r (below the range's total) is given; otherwise the first level's
 // total T yields r = floor(u * T / 2^64).  Returns the index relative to s.o,
@@ -126,19 +148,7 @@ __device__ __forceinline__ int64_t wave_descend(const E& ev, const QuadSlice& s,
   }
   uint64_t w[4] = {0, 0, 0, 0};
   if ((uint32_t)lane < len) quad_weights(ev, s, lo + lane, w);
-  const uint64_t c0 = w[0], c1 = c0 + w[1], c2 = c1 + w[2], tot = c2 + w[3];
-  const uint64_t incl = wave_incl_scan(tot);
-  if (!have_r) {
-    const uint64_t total = readlane64(incl, kWave - 1);
-    if (total == 0) return -1;
-    r = scale_draw(u, total);
-  }
-  const uint64_t m = ballot(incl > r);
-  const int L = m ? first_lane(m) : (int)(len ? len : 1) - 1;
-  const uint64_t rr = r - (incl - tot);  // meaningful in lane L
-  const uint32_t j = rr < c0 ? 0u : rr < c1 ? 1u : rr < c2 ? 2u : 3u;
-  const uint32_t jl = readlane32(j, L);
-  return (int64_t)(4 * (lo + (uint32_t)L) + jl) - (int64_t)s.lead;
+  return pick_in_quads(w, s, lo, len, r, have_r, u);
 }
 
 // Given r below the total of quads [lo, lo + len), returns the relative index
