@@ -30,12 +30,15 @@ namespace fw {
 
 extern __shared__ __attribute__((aligned(16))) uint32_t fw_dyn_lds[];
 
-constexpr uint32_t kFib = 0x9E3779B1u;
+constexpr uint32_t kFib24 = 0x9E3779u;  // 2^24 / golden ratio
 
 // Bucket of key u in a table of 2^(32 - shift) buckets (Fibonacci hashing:
-// the top bits of u times 2^32 / golden ratio).
+// the top bits of the low word of u times 2^24 / golden ratio).  The 24-bit
+// multiply runs at the full VALU rate (a 32-bit one at a quarter); ids from
+// 2^24 on hash by their low 24 bits, which costs probes, never exactness.
+// (HIP's __umul24 returns a signed int: go through uint32_t.)
 __device__ __forceinline__ uint32_t bucket_of(uint32_t u, uint32_t shift) {
-  return (u * kFib) >> shift;
+  return (uint32_t)__umul24(u, kFib24) >> shift;
 }
 constexpr int kGroups = 4;  // queries per wavefront
 constexpr int kGroupLanes = 16;
@@ -47,12 +50,14 @@ __device__ __forceinline__ uint32_t log2_ceil(uint64_t x) {
   return b;
 }
 
-__device__ __forceinline__ uint32_t max4(uint4 v) { return max(max(v.x, v.y), max(v.z, v.w)); }
-
 // u is one of the four cells: the smallest XOR with u is 0.
 __device__ __forceinline__ bool has4(uint4 v, uint32_t u) {
   return min(min(v.x ^ u, v.y ^ u), min(v.z ^ u, v.w ^ u)) == 0u;
 }
+
+// The bucket has a free cell.  Cells fill in order (an insert takes the first
+// free one), so that is the last cell being free.
+__device__ __forceinline__ bool open4(uint4 v) { return v.w == kEnd; }
 
 // Membership in N(prev) for one node2vec hop, by a wave-uniform mode:
 //   0  binary search of the sorted row in global memory;
@@ -78,7 +83,7 @@ struct MemberAny {
       b = (b + 1) & bmask;
       const uint4 v = bucket(b);
       if (has4(v, u)) return true;
-      if (max4(v) == kEnd) return false;
+      if (open4(v)) return false;
     }
   }
   __device__ __forceinline__ bool contains(uint32_t u) const {
@@ -102,7 +107,7 @@ struct MemberAny {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         hit[j] = has4(v[j], u[j]);
-        open[j] = max4(v[j]) == kEnd;
+        open[j] = open4(v[j]);
         more |= !(hit[j] | open[j]);
       }
       if (more) {
