@@ -326,13 +326,16 @@ __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, con
     sub += W;
   }
   cursor += below;
-  const uint32_t fo = ev.f_out, fi = ev.f_in, fr = ev.f_ret;
+  uint32_t f[4];
+  ev.node2vec_factors4(key, in, f);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    uint32_t f = in[j] ? fi : fo;
-    f = key[j] == ev.prev ? fr : f;
-    const uint32_t wj = ((keep >> j) & 1u) ? wq[j] : 0u;
-    out[j] = ev.narrow ? (uint64_t)(uint32_t)__umul24(wj, f) : (uint64_t)wj * f;
+  for (int j = 0; j < 4; ++j) wq[j] = ((keep >> j) & 1u) ? wq[j] : 0u;
+  if (ev.narrow) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = (uint64_t)(uint32_t)__umul24(wq[j], f[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = (uint64_t)wq[j] * f[j];
   }
 }
 
