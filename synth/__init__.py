@@ -271,8 +271,11 @@ def _key(recipe: dict) -> str:
 
 
 def load_recipe_graph(name: str, use_cache: bool = True) -> Graph:
-    """Generate (or read back from the on-disk cache) the graph of a recipe."""
+    """Generate (or read back from the on-disk cache) the graph of a recipe.
+    FW_GRAPH_CACHE=off generates without reading or writing the cache."""
     recipe = RECIPES[name]
+    if os.environ.get("FW_GRAPH_CACHE") == "off":
+        use_cache = False
     d = cache_dir() / _key(recipe)
     parts = ["offsets", "adj", "weights", "labels"]
     if use_cache and (d / "meta.json").exists():

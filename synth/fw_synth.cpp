@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -182,6 +183,14 @@ struct ChungLuSource : EdgeSource {
   }
 };
 
+// Large graphs take minutes: their builds report each finished phase on stderr.
+void progress(uint64_t m, const char* phase) {
+  if (m >= (1ull << 28)) {
+    std::fprintf(stderr, "[synth] %llu draws: %s\n", (unsigned long long)m, phase);
+    std::fflush(stderr);
+  }
+}
+
 int build_csr(const EdgeSource& src, uint64_t nv, int nthreads, uint64_t** offsets_out,
               uint32_t** adj_out, uint64_t* ne_out) {
   if (nthreads < 1) nthreads = 1;
@@ -198,6 +207,7 @@ int build_csr(const EdgeSource& src, uint64_t nv, int nthreads, uint64_t** offse
         __atomic_fetch_add(&deg[v], 1u, __ATOMIC_RELAXED);
       }
   });
+  progress(m, "degrees counted");
   off[0] = 0;
   for (uint64_t i = 0; i < nv; ++i) off[i + 1] = off[i] + deg[i];
   const uint64_t raw = off[nv];
@@ -215,6 +225,7 @@ int build_csr(const EdgeSource& src, uint64_t nv, int nthreads, uint64_t** offse
       }
   });
   std::free(cur);
+  progress(m, "edges scattered");
   // Sort and deduplicate each row.
   parallel_rows(nv, nthreads, [&](uint64_t r) {
     uint32_t* b = tmp + off[r];
@@ -222,6 +233,7 @@ int build_csr(const EdgeSource& src, uint64_t nv, int nthreads, uint64_t** offse
     std::sort(b, e);
     deg[r] = (uint32_t)(std::unique(b, e) - b);
   });
+  progress(m, "rows sorted and deduplicated");
   uint64_t* noff = (uint64_t*)std::malloc((nv + 1) * sizeof(uint64_t));
   if (!noff) { std::free(deg); std::free(off); std::free(tmp); return -1; }
   noff[0] = 0;
