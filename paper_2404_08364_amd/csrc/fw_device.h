@@ -246,6 +246,14 @@ struct MemberGlobal {
   __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
     row_contains4(adj, po, pd, u, hit);
   }
+  // f[j] = fin if u[j] is in the row, else fout.
+  __device__ __forceinline__ void factors4(const uint32_t u[4], uint32_t fin, uint32_t fout,
+                                           uint32_t f[4]) const {
+    bool hit[4];
+    row_contains4(adj, po, pd, u, hit);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f[j] = hit[j] ? fin : fout;
+  }
 };
 
 template <int ALGO, bool WEIGHTED, class MEM = MemberGlobal>
@@ -321,10 +329,12 @@ struct Eval {
       const uint4 a = *reinterpret_cast<const uint4*>(
           reinterpret_cast<const char*>(adj + qa) + q * 16u);
       const uint32_t u[4] = {a.x, a.y, a.z, a.w};
-      bool in[4];
-      mem.contains4(u, in);
+      // f_in for a neighbour of prev, f_out otherwise, then f_ret for prev.
       uint32_t f[4];
-      node2vec_factors4(u, in, f);
+      mem.factors4(u, f_in, f_out, f);
+      const uint32_t fr = f_ret;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) f[j] = u[j] == prev ? fr : f[j];
       if (narrow) {
         // (HIP's __umul24 returns a signed int: go through uint32_t.)
 #pragma unroll

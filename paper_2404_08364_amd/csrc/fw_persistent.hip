@@ -119,6 +119,40 @@ struct MemberAny {
     }
     row_contains4(adj, po, pd, u, hit);
   }
+  // f[j] = fin if u[j] is in N(prev), else fout.  Choosing the factor inside
+  // the lookup keeps the hits in lane masks on the common path; only the
+  // rare longer probes update a factor under a lane mask.
+  __device__ __forceinline__ void factors4(const uint32_t u[4], uint32_t fin, uint32_t fout,
+                                           uint32_t f[4]) const {
+    if (mode == 1) {
+      uint32_t b[4];
+      uint4 v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        b[j] = bucket_of(u[j], shift);
+        v[j] = bucket(b[j]);
+      }
+      bool more = false;
+      bool done[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool hit = has4(v[j], u[j]);
+        f[j] = hit ? fin : fout;
+        done[j] = hit | open4(v[j]);
+        more |= !done[j];
+      }
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (!done[j]) f[j] = probe_rest(u[j], b[j]) ? fin : fout;
+      }
+      return;
+    }
+    bool hit[4];
+    row_contains4(adj, po, pd, u, hit);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f[j] = hit[j] ? fin : fout;
+  }
 };
 
 struct Table {

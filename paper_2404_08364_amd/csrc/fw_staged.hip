@@ -65,6 +65,12 @@ struct MemberLds {
 #pragma unroll
     for (int j = 0; j < 4; ++j) hit[j] = contains(u[j]);
   }
+  // f[j] = fin if u[j] is in the set, else fout.
+  __device__ __forceinline__ void factors4(const uint32_t u[4], uint32_t fin, uint32_t fout,
+                                           uint32_t f[4]) const {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f[j] = contains(u[j]) ? fin : fout;
+  }
 };
 
 struct HashTable {
