@@ -1,7 +1,8 @@
 """Parity at the workloads' full sizes (GPU), in the launch configuration the
 bench times: the whole query set runs on the GPU, and a deterministic sample
-of rows (strided query ids plus the queries that start at the highest-degree
-vertices) is recomputed by the oracle, one query at a time, bit-exact.
+of rows (65,536 strided query ids plus the queries that start at the 1,024
+highest-degree vertices) is recomputed by the oracle, one query at a time,
+bit-exact.
 Every walk depends only on (graph, parameters, seed, query id, start), so a
 sample checks exactly the rows it contains."""
 import os
@@ -66,23 +67,23 @@ def _run(recipe, mode, n_strided, n_top, tune=True):
 def test_rmat22_node2vec_full_size(mode):
     """R-MAT scale 22, edge factor 16, Zipf weights, node2vec p=1 q=2, all
     4,194,304 queries, 80 hops."""
-    _run("rmat22_n2v", mode, 3000, 200)
+    _run("rmat22_n2v", mode, 65536, 1024)
 
 
 def test_rmat22_deepwalk_full_size():
-    _run("rmat22_deepwalk", "persistent", 3000, 200)
+    _run("rmat22_deepwalk", "persistent", 65536, 1024)
 
 
 def test_chunglu24_metapath_full_size():
     """Chung-Lu 2^24 vertices (gamma 2.1, d_max ~0.94M), MetaPath
     [0,1,2,3,4] cycled, all 16,777,216 queries, 20 hops."""
-    got = _run("chunglu24_metapath", "persistent", 4000, 300)
+    got = _run("chunglu24_metapath", "persistent", 65536, 1024)
     assert (got[:, 1] != 0xFFFFFFFF).any()
 
 
 def test_rmat22_ppr_full_size():
     """PPR from the vertex of largest degree (163,319 neighbours) for all
     4,194,304 queries, stop chance 1/5, at most 80 hops."""
-    got = _run("rmat22_ppr", "persistent", 3000, 0)
+    got = _run("rmat22_ppr", "persistent", 65536, 0)
     hops = (got[:, 1:] != 0xFFFFFFFF).sum(axis=1)
     assert (hops == 0).any() and hops.mean() > 2
