@@ -87,3 +87,35 @@ def test_rmat22_ppr_full_size():
     got = _run("rmat22_ppr", "persistent", 65536, 0)
     hops = (got[:, 1:] != 0xFFFFFFFF).sum(axis=1)
     assert (hops == 0).any() and hops.mean() > 2
+
+
+@pytest.mark.skipif(os.environ.get("FW_FULL_PARITY") != "1",
+                    reason="all 4,194,304 rows take about 11 minutes of oracle time on 16 "
+                           "host threads; run with FW_FULL_PARITY=1")
+def test_rmat22_node2vec_all_rows():
+    """Every row of the R-MAT-22 node2vec workload (4,194,304 queries, 80 hops)
+    against the oracle, in slices of 65,536 queries (progress on stdout)."""
+    torch = torch_or_skip()
+    from paper_2404_08364_amd import flowwalk as fw
+    recipe = "rmat22_n2v"
+    g = synth.load_recipe_graph(recipe)
+    walk = synth.RECIPES[recipe]["walk"]
+    (pn, pd), (qn, qd) = walk["p"], walk["q"]
+    f = fw.node2vec_factors(pn, pd, qn, qd)
+    L, seed = walk["length"], walk["seed"]
+    starts = synth.recipe_starts(recipe, g)
+    G = fw.Graph.of(g)
+    st = torch.from_numpy(starts.view(np.int32)).cuda()
+    fw.autotune(G, "node2vec", fw.make_params(f), st[:: max(1, len(starts) // 65536)].contiguous(),
+                L, seed)
+    got = fw.walk(G, "node2vec", fw.make_params(f), st, L, seed, mode="persistent")
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().view(np.uint32)
+    G.free()
+    oprm = oracle.params(*f)
+    n = starts.shape[0]
+    for lo in range(0, n, 65536):
+        qids = np.arange(lo, min(n, lo + 65536), dtype=np.uint64)
+        exp = oracle.walk_ids_threaded(g, "node2vec", oprm, starts, qids, L, seed, THREADS)
+        assert_rows_equal(got[lo: lo + len(qids)], exp, f"{recipe} rows {lo}..")
+        print(f"rows {lo + len(qids)}/{n} identical", flush=True)
