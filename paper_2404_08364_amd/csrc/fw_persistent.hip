@@ -181,12 +181,15 @@ __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restric
     if (tb.cells >= 4 * kWave) tb.kind = 2;
     return;
   }
-  uint32_t bits = log2_ceil((2 * tb.pd + 3) / 4);
-  if (bits < 2) bits = 2;
+  // The table takes the whole region: a smaller N(prev) gets a lower load,
+  // and a lookup then almost never needs a second bucket (with 64 lanes and
+  // four lookups each, any lane needing one costs the whole wavefront).
+  const uint32_t bits = log2_ceil(tb.cells / 4);  // cells: a power of two >= 64
   tb.bmask = (1u << bits) - 1;
   tb.shift = 32 - bits;
-  const uint32_t cells = 4u << bits;
-  for (uint32_t i = lane; i < cells; i += kWave) fw_dyn_lds[tb.base + i] = kEnd;
+  const uint4 empty = make_uint4(kEnd, kEnd, kEnd, kEnd);
+  for (uint32_t i = lane; i < tb.cells / 4; i += kWave)
+    reinterpret_cast<uint4*>(fw_dyn_lds + tb.base)[i] = empty;
   wave_sync_lds();
   for (uint64_t i = lane; i < tb.pd; i += kWave) {
     const uint32_t u = adj[tb.po + i];

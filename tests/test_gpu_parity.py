@@ -85,18 +85,16 @@ def test_powerlaw_graph(env, powerlaw, mode, algo, factors, schema):
     _check(env, g, algo, factors, schema, starts, 12, 31337, mode)
 
 
-def _colliding_graph(npd, nother=150, V=6000, seed=1):
+def _colliding_graph(npd, nother=150, V=40_000, seed=1):
     """Vertex 0 (prev) whose npd neighbours all fall into one bucket of the
-    persistent walker's LDS hash set (Fibonacci hashing, top bits of
-    (u mod 2^24) * 0x9E3779 mod 2^32), so membership tests of vertex 1's neighbours
-    must probe long bucket chains; every walk goes 0 -> 1 -> ..."""
-    pd = npd + 1
-    bits = 2
-    while (1 << bits) < (2 * pd + 3) // 4:
-        bits += 1
-    shift = 32 - bits
-    h = lambda u: (((u & 0xFFFFFF) * 0x9E3779) & 0xFFFFFFFF) >> shift  # noqa: E731
+    persistent walker's LDS hash set (Fibonacci hashing: the top bits of
+    (u mod 2^24) * 0x9E3779 mod 2^32; a table fills its wavefront's region, so
+    keys sharing the top 8 bits share a bucket in every table of up to 256
+    buckets), so membership tests of vertex 1's neighbours must probe long
+    bucket chains; every walk goes 0 -> 1 -> ..."""
+    h = lambda u: (((u & 0xFFFFFF) * 0x9E3779) & 0xFFFFFFFF) >> 24  # noqa: E731
     keys = [u for u in range(2, V) if h(u) == h(2)][:npd]
+    assert len(keys) == npd
     rng = np.random.default_rng(seed)
     ks = set(keys)
     others = [u for u in rng.permutation(np.arange(2, V)).tolist() if u not in ks][:nother]
@@ -106,9 +104,10 @@ def _colliding_graph(npd, nother=150, V=6000, seed=1):
     return csr_from_edges(V, sorted(set(edges)))
 
 
-@pytest.mark.parametrize("npd,V", [(30, 6000), (60, 6000), (120, 12_000), (300, 120_000)])
+@pytest.mark.parametrize("npd,V", [(30, 12_000), (60, 24_000), (120, 40_000), (300, 120_000)])
 def test_hash_bucket_collisions(env, npd, V):
-    """Tables of 16 to 256 buckets with one bucket chain holding every key."""
+    """Every key of N(prev) in one bucket chain, in tables of 64 and 256
+    buckets (regions of 256 and 1024 cells)."""
     torch, fw = env
     g = _colliding_graph(npd, V=V)
     starts = np.zeros(5000, dtype=np.uint32)
@@ -116,38 +115,6 @@ def test_hash_bucket_collisions(env, npd, V):
                  dict(hash_cells=256, wgs_per_cu=4, tiny_max=16)]:
         _check(env, g, "node2vec", (1, 2, 4), (), starts, 3, 777, "persistent",
                tune=fw.make_tune(**tune))
-
-
-def _window_graph(n_prev, prev_step, n_cur, cur_step, V=40_000, dup_every=37):
-    """Vertex 0 (prev) and vertex 1 (cur) with neighbours spread over the same
-    id range at different densities, parallel edges in both rows, and a
-    heavy edge 0 -> 1, so most walks from 0 take the hop 1 -> ? with prev 0.
-    A dense N(prev) gives the merge of sorted rows windows far longer than the
-    LDS region (taken in sub-windows); a sparse one gives short windows."""
-    prev = [2 + prev_step * i for i in range(n_prev)]
-    cur = [2 + cur_step * i for i in range(n_cur)]
-    edges = [(0, 1, 1_000_000, 0)]
-    edges += [(0, k, 1 + k % 3, 0) for k in prev] + [(0, k, 5, 0) for k in prev[::dup_every]]
-    edges += [(1, k, 1 + k % 7, 0) for k in cur] + [(1, k, 9, 0) for k in cur[::dup_every]]
-    edges += [(i, i + 1, 1, 0) for i in range(2, V - 1)]
-    return csr_from_edges(V, sorted(set(edges)), symmetric=False)
-
-
-@pytest.mark.parametrize("shape", [(2000, 1, 400, 7), (3000, 1, 2000, 1), (600, 7, 4200, 1),
-                                   (1500, 3, 1100, 5)])
-def test_merge_windows(env, shape):
-    """node2vec hops whose N(prev) is too large for the LDS hash set: merge
-    windows shorter than a staging round, and longer than the whole region."""
-    torch, fw = env
-    g = _window_graph(*shape)
-    starts = np.zeros(3000, dtype=np.uint32)
-    for tune in [dict(hash_cells=1024, wgs_per_cu=8, tiny_max=16),
-                 dict(hash_cells=512, wgs_per_cu=8, tiny_max=0),
-                 dict(hash_cells=256, wgs_per_cu=4, tiny_max=16)]:
-        _check(env, g, "node2vec", (1, 2, 4), (), starts, 4, 4242, "persistent",
-               tune=fw.make_tune(**tune))
-    for mode in ("plain", "staged"):
-        _check(env, g, "node2vec", (1, 2, 4), (), starts, 4, 4242, mode)
 
 
 @pytest.mark.parametrize("mode", MODES)
