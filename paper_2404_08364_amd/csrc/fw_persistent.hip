@@ -221,20 +221,18 @@ __device__ __forceinline__ void lds_step4(lds_ptr p[4], const uint32_t u[4], uin
 }
 
 // Four lower-bound searches in the sorted LDS run fw_dyn_lds[b, b + n), one
-// trip count for all lanes (n is wave-uniform): lb[j] is the number of
-// entries below u[j], hit[j] whether u[j] occurs in the run.  With P the
+// trip count for all lanes (n is wave-uniform): hit[j] says whether u[j]
+// occurs in the run.  The cell after the run, fw_dyn_lds[b + n], must hold a
+// value above every key.  With P the
 // largest power of two not above n, one probe at n - P - 1 leaves a range of
 // P + 1 candidates, which halving steps narrow to two; the last five steps
 // (h = 16 .. 1) are unrolled and entered by a switch, so their probe offsets
 // and increments are immediates (4h <= 64 is an inline constant).
 __device__ __forceinline__ void lds_search4(uint32_t b, uint32_t n, const uint32_t u[4],
-                                            uint32_t lb[4], bool hit[4]) {
+                                            bool hit[4]) {
   if (n == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      lb[j] = 0;
-      hit[j] = false;
-    }
+    for (int j = 0; j < 4; ++j) hit[j] = false;
     return;
   }
   const lds_ptr run = (lds_ptr)(fw_dyn_lds + b);
@@ -255,14 +253,12 @@ __device__ __forceinline__ void lds_search4(uint32_t b, uint32_t n, const uint32
     case 1: lds_step4(p, u, 1); [[fallthrough]];
     default: break;
   }
+  // The lower bound is p or p + 1; the run is followed by a sentinel above
+  // every key, so p[1] is always there to read.
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t i = (uint32_t)(p[j] - run);  // the lower bound is i or i + 1
-    const uint32_t x0 = run[i];
-    const uint32_t x1 = run[min(i + 1, n - 1)];
-    const bool lt = x0 < u[j];
-    lb[j] = i + (lt ? 1u : 0u);
-    hit[j] = (x0 == u[j]) | (lt & (i + 1 < n) & (x1 == u[j]));
+    const uint32_t x0 = p[j][0], x1 = p[j][1];
+    hit[j] = (x0 == u[j]) | ((x0 < u[j]) & (x1 == u[j]));
   }
 }
 
@@ -275,7 +271,7 @@ __device__ __forceinline__ void lds_search4(uint32_t b, uint32_t n, const uint32
 // keys are looked up there by binary search.  A run too long for the region
 // is taken in region-sized sub-windows whose lookups are or-ed.  Entries
 // below kmax cannot match a later key, so the cursor then moves past them
-// (their count is the sum of kmax's lower bounds in the sub-windows).  out[j]
+// (the staging rounds count them by ballots).  out[j]
 // is the transition weight of entry j of the lane's quad (0 outside the
 // slice or the chunk).
 template <class E>
@@ -309,7 +305,7 @@ __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, con
                                    (int)L);
   bool in[4] = {false, false, false, false};
   uint64_t sub = cursor;  // first entry of the current sub-window
-  uint64_t below = 0;     // entries below kmax in the sub-windows so far
+  uint64_t below = 0;     // entries below kmax staged so far (every entry is staged once)
   for (;;) {
     // Stage N(prev)[sub, sub + W): the entries <= kmax (a prefix, N(prev)
     // being sorted), or as many full rounds of them as the region holds.
@@ -326,10 +322,12 @@ __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, con
       const uint32_t x0 = k0 < left ? v0 : kEnd;  // kEnd is above every key
       fw_dyn_lds[tb.base + k0] = x0;
       W = (uint32_t)__builtin_popcountll(ballot(x0 <= kmax));
+      below += (uint32_t)__builtin_popcountll(ballot(x0 < kmax));
       bool full = W == (uint32_t)kWave;
       while (full) {
-        if (W + 4 * kWave > tb.cells) {
+        if (W + 4 * kWave + 1 > tb.cells) {  // one cell stays for the sentinel
           more = true;
+          fw_dyn_lds[tb.base + W] = kEnd;  // every lane writes the same value
           break;
         }
         // All four loads first, then the stores and counts.
@@ -346,18 +344,17 @@ __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, con
           const uint32_t x = k < left ? v[j] : kEnd;
           fw_dyn_lds[tb.base + k] = x;
           n_le += (uint32_t)__builtin_popcountll(ballot(x <= kmax));
+          below += (uint32_t)__builtin_popcountll(ballot(x < kmax));
         }
         W += n_le;
         full = n_le == 4u * kWave;
       }
     }
     wave_sync_lds();
-    uint32_t lb[4];
     bool h[4];
-    lds_search4(tb.base, W, key, lb, h);
+    lds_search4(tb.base, W, key, h);
 #pragma unroll
     for (int j = 0; j < 4; ++j) in[j] |= h[j];
-    below += readlane32(jl == 0 ? lb[0] : jl == 1 ? lb[1] : jl == 2 ? lb[2] : lb[3], (int)L);
     wave_sync_lds();
     if (!more) break;
     sub += W;
