@@ -299,20 +299,6 @@ struct Eval {
   // included: the caller masks them.  The offset from the uniform base qa is
   // 32-bit (slices are < 2^28 entries), so each load is one scalar base plus
   // one vector offset.
-  // Node2vec factor of each of four neighbours u[j] (membership in[j]): f_ret
-  // for prev, f_in for a neighbour of prev, f_out otherwise.
-  __device__ __forceinline__ void node2vec_factors4(const uint32_t u[4], const bool in[4],
-                                                    uint32_t f[4]) const {
-    // Selects between uniform copies (selecting struct members directly
-    // would let the compiler address the struct in scratch).
-    const uint32_t fo = f_out, fi = f_in, fr = f_ret;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      f[j] = in[j] ? fi : fo;
-      f[j] = u[j] == prev ? fr : f[j];
-    }
-  }
-
   __device__ __forceinline__ void quad(uint32_t q, uint64_t out[4]) const {
     uint32_t wq[4] = {1u, 1u, 1u, 1u};
     if (WEIGHTED) {

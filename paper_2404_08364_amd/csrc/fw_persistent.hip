@@ -273,11 +273,11 @@ __device__ __forceinline__ void lds_search4(uint32_t b, uint32_t n, const uint32
 // below kmax cannot match a later key, so the cursor then moves past them
 // (the staging rounds count them by ballots).  out[j]
 // is the transition weight of entry j of the lane's quad (0 outside the
-// slice or the chunk).
+// slice or the chunk), sum their total.
 template <class E>
 __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, const Table& tb,
                                             uint32_t c0, uint32_t ge, uint64_t& cursor,
-                                            int lane, uint64_t out[4]) {
+                                            int lane, uint64_t out[4], uint64_t& sum) {
   const char* __restrict__ wrun = reinterpret_cast<const char*>(ev.w + s.a);
   const char* __restrict__ arun = reinterpret_cast<const char*>(ev.adj + s.a);
   const uint32_t* __restrict__ prow = ev.adj + tb.po;  // N(prev)
@@ -303,7 +303,9 @@ __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, con
   const uint32_t jl = (c0 + L + 1 == s.nq) ? jend : 3u;
   const uint32_t kmax = readlane32(jl == 0 ? key[0] : jl == 1 ? key[1] : jl == 2 ? key[2] : key[3],
                                    (int)L);
-  bool in[4] = {false, false, false, false};
+  // Factor per key: f_out until a sub-window's lookup finds the key.
+  uint32_t fo = ev.f_out, fi = ev.f_in;
+  uint32_t f[4] = {fo, fo, fo, fo};
   uint64_t sub = cursor;  // first entry of the current sub-window
   uint64_t below = 0;     // entries below kmax staged so far (every entry is staged once)
   for (;;) {
@@ -354,22 +356,31 @@ __device__ __forceinline__ void merge_chunk(const E& ev, const QuadSlice& s, con
     bool h[4];
     lds_search4(tb.base, W, key, h);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) in[j] |= h[j];
+    for (int j = 0; j < 4; ++j) f[j] = h[j] ? fi : f[j];
     wave_sync_lds();
     if (!more) break;
     sub += W;
   }
   cursor += below;
-  uint32_t f[4];
-  ev.node2vec_factors4(key, in, f);
+  const uint32_t fr = ev.f_ret;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) wq[j] = ((keep >> j) & 1u) ? wq[j] : 0u;
+  for (int j = 0; j < 4; ++j) f[j] = key[j] == ev.prev ? fr : f[j];
+  if (keep != 0xFu) {  // the slice's first or last quad, or a lane past the chunk
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wq[j] = ((keep >> j) & 1u) ? wq[j] : 0u;
+  }
   if (ev.narrow) {
+    uint32_t p[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) out[j] = (uint64_t)(uint32_t)__umul24(wq[j], f[j]);
+    for (int j = 0; j < 4; ++j) {
+      p[j] = (uint32_t)__umul24(wq[j], f[j]);  // (HIP's __umul24 returns an int)
+      out[j] = p[j];
+    }
+    sum = (uint64_t)((p[0] + p[1]) + (p[2] + p[3]));  // four products below 2^24
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j) out[j] = (uint64_t)wq[j] * f[j];
+    sum = (out[0] + out[1]) + (out[2] + out[3]);
   }
 }
 
@@ -390,9 +401,9 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
     if ((uint32_t)lane == g) gcur = cursor;
     uint64_t acc = 0;
     for (uint32_t c0 = gb; c0 < ge; c0 += kWave) {
-      uint64_t w[4];
-      merge_chunk(ev, s, tb, c0, ge, cursor, lane, w);
-      acc += (w[0] + w[1]) + (w[2] + w[3]);
+      uint64_t w[4], t;
+      merge_chunk(ev, s, tb, c0, ge, cursor, lane, w, t);
+      acc += t;
     }
     const uint64_t tot = wave_sum(acc);
     if ((uint32_t)lane == g) mine = tot;
@@ -620,8 +631,8 @@ k_walk_persistent(
             // A one-chunk group (rows up to 16,384 entries): merge it again
             // from its cursor and pick inside it.
             uint64_t cur = readlane64(gcur, gs);
-            uint64_t w[4];
-            merge_chunk(ev, qs, tb, lo, lo + len, cur, lane, w);
+            uint64_t w[4], t;
+            merge_chunk(ev, qs, tb, lo, lo + len, cur, lane, w, t);
             idx = pick_in_quads(w, qs, lo, len, r, true, 0);
           } else {
             idx = (int64_t)wave_locate(ev, qs, lo, len, r);
