@@ -299,6 +299,23 @@ struct Eval {
   // included: the caller masks them.  The offset from the uniform base qa is
   // 32-bit (slices are < 2^28 entries), so each load is one scalar base plus
   // one vector offset.
+  // Total transition weight of quad q (all four entries).  Unweighted
+  // MetaPath counts the matching labels of the quad's word in a few
+  // bit operations (kCheapTotal); everything else sums quad().
+  static constexpr bool kCheapTotal = ALGO == kMetaPath && !WEIGHTED;
+  __device__ __forceinline__ uint64_t quad_total4(uint32_t q) const {
+    if (ALGO == kMetaPath && !WEIGHTED) {
+      const uint32_t l = *reinterpret_cast<const uint32_t*>(
+          reinterpret_cast<const char*>(lab + qa) + q * 4u);
+      const uint32_t x = l ^ (want * 0x01010101u);  // zero bytes: matching labels
+      const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
+      return (uint64_t)__builtin_popcount(z);
+    }
+    uint64_t o[4];
+    quad(q, o);
+    return (o[0] + o[1]) + (o[2] + o[3]);
+  }
+
   __device__ __forceinline__ void quad(uint32_t q, uint64_t out[4]) const {
     uint32_t wq[4] = {1u, 1u, 1u, 1u};
     if (WEIGHTED) {

@@ -30,6 +30,12 @@ struct TaskEval {
   uint64_t end;  // n_tasks * size
   uint64_t qa;   // quad run base (set by bind_quads)
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return w[o + i]; }
+  static constexpr bool kCheapTotal = false;
+  __device__ __forceinline__ uint64_t quad_total4(uint32_t q) const {
+    uint64_t o[4];
+    quad(q, o);
+    return (o[0] + o[1]) + (o[2] + o[3]);
+  }
   __device__ __forceinline__ void quad(uint32_t q, uint64_t out[4]) const {
     const uint64_t p = qa + 4ull * q;
     if (p + 4 <= end) {

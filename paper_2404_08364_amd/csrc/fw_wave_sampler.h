@@ -88,9 +88,21 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
     // latency, and the second copy of the evaluator would spill registers.
 #pragma unroll 1
     for (uint32_t q = gb + lane; q < ge; q += kWave) {
-      uint64_t w[4];
-      quad_weights(ev, s, q, w);
-      acc += (w[0] + w[1]) + (w[2] + w[3]);
+      if constexpr (E::kCheapTotal) {
+        // Interior quads by the evaluator's own total (a second, small copy
+        // of the evaluator; the weights are only needed at the boundary).
+        if (q == 0 || q + 1 == s.nq) {
+          uint64_t w[4];
+          quad_weights(ev, s, q, w);
+          acc += (w[0] + w[1]) + (w[2] + w[3]);
+        } else {
+          acc += ev.quad_total4(q);
+        }
+      } else {
+        uint64_t w[4];
+        quad_weights(ev, s, q, w);
+        acc += (w[0] + w[1]) + (w[2] + w[3]);
+      }
     }
     const uint64_t tot = wave_sum(acc);
     if ((uint32_t)lane == g) mine = tot;
