@@ -156,6 +156,17 @@ def copy_bandwidth(torch, dev, nbytes=2 << 30, reps=5):
     return 2 * nbytes / (float(np.median(ms)) / 1e3) / 1e9
 
 
+def _cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "" where unreadable."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -182,6 +193,7 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
     return dict(value=hops / wall, unit="walk steps/s", cores=threads, kind="oracle",
                 sample=f"{len(qids)} queries (every {step}-th query id), {hops} hops, "
                        f"{wall:.1f} s wall on {threads} host threads",
+                cpu_model=_cpu_model(), host_cpus=os.cpu_count(),
                 parity_on_sample=ok,
                 one_core=dict(value=hops1 / wall1, queries=len(q1), hops=hops1,
                               seconds=wall1))
