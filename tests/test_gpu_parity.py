@@ -85,6 +85,22 @@ def test_powerlaw_graph(env, powerlaw, mode, algo, factors, schema):
     _check(env, g, algo, factors, schema, starts, 12, 31337, mode)
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("schema", [(0x80, 0xFF, 0x7F), (0x00, 0x01, 0xFE, 0x81), (0x55,)])
+def test_metapath_label_bytes(env, mode, schema):
+    """Unweighted MetaPath with labels over the whole byte range (the walkers
+    count matching label bytes of a quad with bit operations): bytes whose
+    high bit or low seven bits equal the wanted label's must not count."""
+    g = synth.chung_lu(20_000, 300_000, 2.1, 1.5, seed=9)
+    rng = np.random.default_rng(10)
+    pool = np.array(sorted({*schema, *(b ^ 0x80 for b in schema), *(b ^ 0x01 for b in schema),
+                            0x00, 0x7F, 0x80, 0xFF}), dtype=np.uint8)
+    g.labels = pool[rng.integers(0, len(pool), g.n_edges)]
+    g.weights = None
+    starts = np.arange(g.n_vertices, dtype=np.uint32)[::4]
+    _check(env, g, "metapath", (1, 1, 1), schema, starts, 10, 2718, mode)
+
+
 def _colliding_graph(npd, nother=150, V=40_000, seed=1):
     """Vertex 0 (prev) whose npd neighbours all fall into one bucket of the
     persistent walker's LDS hash set (Fibonacci hashing: the top bits of
