@@ -161,10 +161,6 @@ __device__ __forceinline__ uint32_t uniform32(uint32_t v) {
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t x) { return readlane64(wave_incl_scan(x), 63); }
 
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
-  return readlane32(wave_incl_scan32(x), 63);
-}
-
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int first_lane(uint64_t mask) { return (int)__builtin_ctzll(mask); }
@@ -243,9 +239,6 @@ struct MemberGlobal {
   const uint32_t* __restrict__ adj;
   uint64_t po, pd;
   __device__ __forceinline__ bool contains(uint32_t u) const { return row_contains(adj, po, pd, u); }
-  __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
-    row_contains4(adj, po, pd, u, hit);
-  }
   // f[j] = fin if u[j] is in the row, else fout.
   __device__ __forceinline__ void factors4(const uint32_t u[4], uint32_t fin, uint32_t fout,
                                            uint32_t f[4]) const {

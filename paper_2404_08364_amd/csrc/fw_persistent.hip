@@ -86,39 +86,6 @@ struct MemberAny {
       if (open4(v)) return false;
     }
   }
-  __device__ __forceinline__ bool contains(uint32_t u) const {
-    bool h[4];
-    const uint32_t q[4] = {u, u, u, u};
-    contains4(q, h);
-    return h[0];
-  }
-  // Four lookups; in the hash-set mode their first probes are issued together.
-  __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
-    if (mode == 1) {
-      uint32_t b[4];
-      uint4 v[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        b[j] = bucket_of(u[j], shift);
-        v[j] = bucket(b[j]);
-      }
-      bool more = false;
-      bool open[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        hit[j] = has4(v[j], u[j]);
-        open[j] = open4(v[j]);
-        more |= !(hit[j] | open[j]);
-      }
-      if (more) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (!(hit[j] | open[j])) hit[j] = probe_rest(u[j], b[j]);
-      }
-      return;
-    }
-    row_contains4(adj, po, pd, u, hit);
-  }
   // f[j] = fin if u[j] is in N(prev), else fout.  Choosing the factor inside
   // the lookup keeps the hits in lane masks on the common path; only the
   // rare longer probes update a factor under a lane mask.

@@ -61,10 +61,6 @@ struct MemberLds {
       b = (b + 1) & bmask;
     }
   }
-  __device__ __forceinline__ void contains4(const uint32_t u[4], bool hit[4]) const {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) hit[j] = contains(u[j]);
-  }
   // f[j] = fin if u[j] is in the set, else fout.
   __device__ __forceinline__ void factors4(const uint32_t u[4], uint32_t fin, uint32_t fout,
                                            uint32_t f[4]) const {
