@@ -371,6 +371,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--use-graph", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--autotune-sample", type=int, default=0,
+                    help="queries the autotuner times (0 = every k-th query, at least "
+                         "65536 and 1/64 of the workload, so that the sample's few long "
+                         "walks do not decide the timings)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="seconds of arrivals per offered rate (0 = no serve phase)")
     ap.add_argument("--serve-rates", default="50,100,250,500,2000",
@@ -464,7 +468,8 @@ def main():
 
     tuned = None
     if args.autotune and args.mode in ("persistent", "auto"):
-        sample = starts[:: max(1, n // 65536)].contiguous()
+        want = args.autotune_sample or max(65536, n // 64)
+        sample = starts[:: max(1, n // want)].contiguous()
         t_at = time.time()
         tuned = fw.autotune(G, algo, prm, sample, L, seed, stream=stream)
         log(f"autotune ({sample.shape[0]} queries, {time.time() - t_at:.1f} s): {tuned}")

@@ -287,14 +287,10 @@ struct Eval {
     }
   }
 
-  // Weights of quad q of the run at qa (the arrays are padded so that a
-  // quad never ends past the allocation), entries outside the slice
-  // included: the caller masks them.  The offset from the uniform base qa is
-  // 32-bit (slices are < 2^28 entries), so each load is one scalar base plus
-  // one vector offset.
-  // Total transition weight of quad q (all four entries).  Unweighted
-  // MetaPath counts the matching labels of the quad's word in a few
-  // bit operations (kCheapTotal); everything else sums quad().
+  // Total transition weight of quad q (all four entries, so interior quads
+  // only).  Unweighted MetaPath counts the matching labels of the quad's
+  // word in a few bit operations (kCheapTotal: the streaming pass then takes
+  // several quads per lane at once); everything else sums quad().
   static constexpr bool kCheapTotal = ALGO == kMetaPath && !WEIGHTED;
   __device__ __forceinline__ uint64_t quad_total4(uint32_t q) const {
     if (ALGO == kMetaPath && !WEIGHTED) {
@@ -309,6 +305,11 @@ struct Eval {
     return (o[0] + o[1]) + (o[2] + o[3]);
   }
 
+  // Weights of quad q of the run at qa (the arrays are padded so that a
+  // quad never ends past the allocation), entries outside the slice
+  // included: the caller masks them.  The offset from the uniform base qa is
+  // 32-bit (slices are < 2^28 entries), so each load is one scalar base plus
+  // one vector offset.
   __device__ __forceinline__ void quad(uint32_t q, uint64_t out[4]) const {
     uint32_t wq[4] = {1u, 1u, 1u, 1u};
     if (WEIGHTED) {

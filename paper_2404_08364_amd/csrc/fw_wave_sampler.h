@@ -84,21 +84,42 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
     const uint32_t gb = lo + g * sp.gsz;
     const uint32_t ge = min(gb + sp.gsz, lo + len);
     uint64_t acc = 0;
-    // Not unrolled: at eight wavefronts per SIMD occupancy hides the load
-    // latency, and the second copy of the evaluator would spill registers.
+    if constexpr (E::kCheapTotal) {
+      // The slice's first and last quads need the masked weights; every
+      // other quad takes the evaluator's own total, a few bit operations on
+      // one small load.  Those loads are short, so eight (then four) quads
+      // per lane are loaded at once to keep enough bytes in flight (sixteen
+      // were slower again).
+      const uint32_t ib = gb > 1u ? gb : 1u;
+      const uint32_t ie = ge < s.nq - 1 ? ge : s.nq - 1;
+      uint32_t q = ib + (uint32_t)lane;
 #pragma unroll 1
-    for (uint32_t q = gb + lane; q < ge; q += kWave) {
-      if constexpr (E::kCheapTotal) {
-        // Interior quads by the evaluator's own total (a second, small copy
-        // of the evaluator; the weights are only needed at the boundary).
-        if (q == 0 || q + 1 == s.nq) {
-          uint64_t w[4];
-          quad_weights(ev, s, q, w);
-          acc += (w[0] + w[1]) + (w[2] + w[3]);
-        } else {
-          acc += ev.quad_total4(q);
-        }
-      } else {
+      for (; q + 7 * kWave < ie; q += 8 * kWave) {
+        uint64_t t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = ev.quad_total4(q + k * kWave);
+        acc += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+      }
+      if (q + 3 * kWave < ie) {
+        const uint64_t t0 = ev.quad_total4(q), t1 = ev.quad_total4(q + kWave),
+                       t2 = ev.quad_total4(q + 2 * kWave), t3 = ev.quad_total4(q + 3 * kWave);
+        acc += (t0 + t1) + (t2 + t3);
+        q += 4 * kWave;
+      }
+#pragma unroll 1
+      for (; q < ie; q += kWave) acc += ev.quad_total4(q);
+      const bool first = gb == 0 && ge > 0 && lane == 0;
+      const bool last = ge == s.nq && s.nq > 1 && gb < ge && lane == 1;
+      if (first || last) {
+        uint64_t w[4];
+        quad_weights(ev, s, first ? 0u : s.nq - 1, w);
+        acc += (w[0] + w[1]) + (w[2] + w[3]);
+      }
+    } else {
+      // Not unrolled: at eight wavefronts per SIMD occupancy hides the load
+      // latency, and a second copy of the evaluator would spill registers.
+#pragma unroll 1
+      for (uint32_t q = gb + lane; q < ge; q += kWave) {
         uint64_t w[4];
         quad_weights(ev, s, q, w);
         acc += (w[0] + w[1]) + (w[2] + w[3]);
