@@ -377,7 +377,7 @@ def main():
                          "walks do not decide the timings)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="seconds of arrivals per offered rate (0 = no serve phase)")
-    ap.add_argument("--serve-rates", default="50,100,250,500,2000",
+    ap.add_argument("--serve-rates", default="50,100,250,500,1000,2000",
                     help="offered request rates (requests/s), comma-separated")
     ap.add_argument("--serve-max-requests", type=int, default=3000)
     ap.add_argument("--serve-workload", default="rmat24_serve")

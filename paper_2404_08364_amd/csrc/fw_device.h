@@ -293,16 +293,25 @@ struct Eval {
   // several quads per lane at once); everything else sums quad().
   static constexpr bool kCheapTotal = ALGO == kMetaPath && !WEIGHTED;
   __device__ __forceinline__ uint64_t quad_total4(uint32_t q) const {
-    if (ALGO == kMetaPath && !WEIGHTED) {
-      const uint32_t l = *reinterpret_cast<const uint32_t*>(
-          reinterpret_cast<const char*>(lab + qa) + q * 4u);
-      const uint32_t x = l ^ (want * 0x01010101u);  // zero bytes: matching labels
-      const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
-      return (uint64_t)__builtin_popcount(z);
-    }
+    if (ALGO == kMetaPath && !WEIGHTED) return (uint64_t)__builtin_popcount(quad_match(q));
     uint64_t o[4];
     quad(q, o);
     return (o[0] + o[1]) + (o[2] + o[3]);
+  }
+
+  // Unweighted MetaPath: bit 7 of byte j is set iff entry j of quad q
+  // carries the wanted label (a zero byte of labels ^ want, found without
+  // carries between bytes).
+  __device__ __forceinline__ uint32_t quad_match(uint32_t q) const {
+    return match_bits(quad_labels(q));
+  }
+  // The four labels of quad q, entry j in byte j.
+  __device__ __forceinline__ uint32_t quad_labels(uint32_t q) const {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(lab + qa) + q * 4u);
+  }
+  __device__ __forceinline__ uint32_t match_bits(uint32_t l) const {
+    const uint32_t x = l ^ (want * 0x01010101u);
+    return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
   }
 
   // Weights of quad q of the run at qa (the arrays are padded so that a

@@ -73,25 +73,37 @@ struct GroupSplit {
   }
 };
 
-// Lane g returns the total of group g of quads [lo, lo + len).  ev is bound.
+// Bit 7 of byte j is set for the entries j of quad q inside the slice.
+__device__ __forceinline__ uint32_t inside_bytes(const QuadSlice& s, uint32_t q) {
+  uint32_t m = 0x80808080u;
+  if (q == 0) m &= 0xFFFFFFFFu << (8 * s.lead);
+  if (q + 1 == s.nq) m &= 0xFFFFFFFFu >> (8 * (3 - ((s.lead + s.d - 1) & 3u)));
+  return m;
+}
+
+// wave_group_totals for an evaluator with a cheap quad total (unweighted
+// MetaPath: one 4-byte load of labels and a few bit operations per quad).
+// A load that short keeps few bytes in flight, so every lane loads several
+// quads before counting.  With eight or more 64-quad chunks per group a lane
+// sums eight quads of a group at a time and one wave sum gives the group's
+// total; with fewer, four consecutive chunks are counted at once and their
+// totals (each at most 256) come from two wave sums of two 16-bit fields.
 template <class E>
-__device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSlice& s,
-                                                      uint32_t lo, uint32_t len,
-                                                      const GroupSplit& sp) {
+__device__ __forceinline__ uint64_t cheap_group_totals(const E& ev, const QuadSlice& s,
+                                                       uint32_t lo, uint32_t len,
+                                                       const GroupSplit& sp) {
   const int lane = lane_id();
+  const uint32_t P = sp.gsz / kWave;  // chunks per group
+  const uint32_t end = lo + len;
   uint64_t mine = 0;
-  for (uint32_t g = 0; g < sp.groups; ++g) {
-    const uint32_t gb = lo + g * sp.gsz;
-    const uint32_t ge = min(gb + sp.gsz, lo + len);
-    uint64_t acc = 0;
-    if constexpr (E::kCheapTotal) {
-      // The slice's first and last quads need the masked weights; every
-      // other quad takes the evaluator's own total, a few bit operations on
-      // one small load.  Those loads are short, so eight (then four) quads
-      // per lane are loaded at once to keep enough bytes in flight (sixteen
-      // were slower again).
+  if (P >= 8) {
+    for (uint32_t g = 0; g < sp.groups; ++g) {
+      const uint32_t gb = lo + g * sp.gsz;
+      const uint32_t ge = min(gb + sp.gsz, end);
+      // The slice's first and last quads are counted with their masks.
       const uint32_t ib = gb > 1u ? gb : 1u;
       const uint32_t ie = ge < s.nq - 1 ? ge : s.nq - 1;
+      uint64_t acc = 0;
       uint32_t q = ib + (uint32_t)lane;
 #pragma unroll 1
       for (; q + 7 * kWave < ie; q += 8 * kWave) {
@@ -100,22 +112,70 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
         for (int k = 0; k < 8; ++k) t[k] = ev.quad_total4(q + k * kWave);
         acc += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
       }
-      if (q + 3 * kWave < ie) {
-        const uint64_t t0 = ev.quad_total4(q), t1 = ev.quad_total4(q + kWave),
-                       t2 = ev.quad_total4(q + 2 * kWave), t3 = ev.quad_total4(q + 3 * kWave);
-        acc += (t0 + t1) + (t2 + t3);
-        q += 4 * kWave;
-      }
 #pragma unroll 1
       for (; q < ie; q += kWave) acc += ev.quad_total4(q);
-      const bool first = gb == 0 && ge > 0 && lane == 0;
-      const bool last = ge == s.nq && s.nq > 1 && gb < ge && lane == 1;
+      const bool first = gb == 0 && lane == 0;
+      const bool last = ge == s.nq && lane == 1;
       if (first || last) {
         uint64_t w[4];
         quad_weights(ev, s, first ? 0u : s.nq - 1, w);
         acc += (w[0] + w[1]) + (w[2] + w[3]);
       }
-    } else {
+      const uint64_t tot = wave_sum(acc);
+      if ((uint32_t)lane == g) mine = tot;
+    }
+    return mine;
+  }
+  uint32_t g = 0, r = 0;  // group of the next chunk, and its place in the group
+#pragma unroll 1
+  for (uint32_t c = lo; c < end; c += 4 * kWave) {
+    // Every lane loads (past the range it re-reads the range's last quad
+    // and counts nothing); the four loads are issued before any is used
+    // (the scheduler would otherwise wait on each in turn).
+    uint32_t l[4], n[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      l[k] = ev.quad_labels(min(c + (uint32_t)k * kWave + (uint32_t)lane, end - 1));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t q = c + (uint32_t)k * kWave + (uint32_t)lane;
+      const uint32_t m = q < end ? inside_bytes(s, q) : 0u;
+      n[k] = (uint32_t)__builtin_popcount(ev.match_bits(l[k]) & m);
+    }
+    uint32_t t[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const uint32_t x = wave_incl_scan32(n[2 * k] | (n[2 * k + 1] << 16));
+      t[k] = (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t tot = (t[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+      if ((uint32_t)lane == g) mine += tot;
+      if (++r == P) {
+        r = 0;
+        ++g;
+      }
+    }
+  }
+  return mine;
+}
+
+// Lane g returns the total of group g of quads [lo, lo + len).  ev is bound.
+template <class E>
+__device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSlice& s,
+                                                      uint32_t lo, uint32_t len,
+                                                      const GroupSplit& sp) {
+  if constexpr (E::kCheapTotal) {
+    return cheap_group_totals(ev, s, lo, len, sp);
+  } else {
+    const int lane = lane_id();
+    uint64_t mine = 0;
+    for (uint32_t g = 0; g < sp.groups; ++g) {
+      const uint32_t gb = lo + g * sp.gsz;
+      const uint32_t ge = min(gb + sp.gsz, lo + len);
+      uint64_t acc = 0;
       // Not unrolled: at eight wavefronts per SIMD occupancy hides the load
       // latency, and a second copy of the evaluator would spill registers.
 #pragma unroll 1
@@ -124,11 +184,11 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
         quad_weights(ev, s, q, w);
         acc += (w[0] + w[1]) + (w[2] + w[3]);
       }
+      const uint64_t tot = wave_sum(acc);
+      if ((uint32_t)lane == g) mine = tot;
     }
-    const uint64_t tot = wave_sum(acc);
-    if ((uint32_t)lane == g) mine = tot;
+    return mine;
   }
-  return mine;
 }
 
 // Last level: lane i holds the weights of quad lo + i (0 for i >= len,

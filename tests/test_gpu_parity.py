@@ -101,6 +101,38 @@ def test_metapath_label_bytes(env, mode, schema):
     _check(env, g, "metapath", (1, 1, 1), schema, starts, 10, 2718, mode)
 
 
+_HUB_ROWS = {}
+
+
+def _labelled_hub(d, lead):
+    """Vertex 1 is a hub of degree d with random labels in {0, 1, 2} and no
+    weights; vertex 0 has `lead` neighbours of its own, so the hub's row
+    starts `lead` entries into a 4-entry quad."""
+    key = (d, lead)
+    if key not in _HUB_ROWS:
+        rng = np.random.default_rng(d * 4 + lead)
+        lab = rng.integers(0, 3, d + lead)
+        edges = [(0, 2 + d + i, 1, int(lab[d + i])) for i in range(lead)]
+        edges += [(1, 2 + i, 1, int(lab[i])) for i in range(d)]
+        _HUB_ROWS[key] = csr_from_edges(2 + d + lead, edges, weights=False)
+    return _HUB_ROWS[key]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("d,lead", [(65, 1), (255, 2), (257, 3), (2049, 0), (2049, 1),
+                                    (16385, 2), (114691, 3), (131073, 1), (300001, 2)])
+def test_metapath_unweighted_hub_rows(env, mode, d, lead):
+    """Unweighted MetaPath counts matching labels per quad in its streaming
+    pass, several quads per lane at once, with the slice's first and last
+    quads masked: hub rows of every length class (one chunk, fewer than eight
+    chunks per group, eight or more) at every alignment of the row's start."""
+    g = _labelled_hub(d, lead)
+    assert int(g.offsets[1]) % 4 == lead
+    starts = np.concatenate([np.ones(96, np.uint32), np.arange(2, 34, dtype=np.uint32)])
+    for schema in [(1,), (2, 0)]:
+        _check(env, g, "metapath", (1, 1, 1), schema, starts, 6, 4242 + d, mode)
+
+
 def _colliding_graph(npd, nother=150, V=40_000, seed=1):
     """Vertex 0 (prev) whose npd neighbours all fall into one bucket of the
     persistent walker's LDS hash set (Fibonacci hashing: the top bits of
