@@ -292,6 +292,12 @@ struct Eval {
   // word in a few bit operations (kCheapTotal: the streaming pass then takes
   // several quads per lane at once); everything else sums quad().
   static constexpr bool kCheapTotal = ALGO == kMetaPath && !WEIGHTED;
+  // Weighted DeepWalk and PPR: a quad's transition weights are its raw
+  // weights (one 16-byte load, quad_raw).
+  static constexpr bool kRawWeights = (ALGO == kDeepWalk || ALGO == kPPR) && WEIGHTED;
+  __device__ __forceinline__ uint4 quad_raw(uint32_t q) const {
+    return *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(w + qa) + q * 16u);
+  }
   __device__ __forceinline__ uint64_t quad_total4(uint32_t q) const {
     if (ALGO == kMetaPath && !WEIGHTED) return (uint64_t)__builtin_popcount(quad_match(q));
     uint64_t o[4];

@@ -31,6 +31,7 @@ struct TaskEval {
   uint64_t qa;   // quad run base (set by bind_quads)
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return w[o + i]; }
   static constexpr bool kCheapTotal = false;
+  static constexpr bool kRawWeights = false;
   __device__ __forceinline__ uint64_t quad_total4(uint32_t q) const {
     uint64_t o[4];
     quad(q, o);

@@ -81,6 +81,16 @@ __device__ __forceinline__ uint32_t inside_bytes(const QuadSlice& s, uint32_t q)
   return m;
 }
 
+// Sum of a quad's raw weights, entries outside the slice left out.
+__device__ __forceinline__ uint64_t raw_quad_sum(const QuadSlice& s, uint32_t q, uint4 v) {
+  uint32_t x[4] = {v.x, v.y, v.z, v.w};
+  if (q == 0 || q + 1 == s.nq) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = s.inside(q, j) ? x[j] : 0u;
+  }
+  return ((uint64_t)x[0] + x[1]) + ((uint64_t)x[2] + x[3]);
+}
+
 // wave_group_totals for an evaluator with a cheap quad total (unweighted
 // MetaPath: one 4-byte load of labels and a few bit operations per quad).
 // A load that short keeps few bytes in flight, so every lane loads several
@@ -169,6 +179,37 @@ __device__ __forceinline__ uint64_t wave_group_totals(const E& ev, const QuadSli
                                                       const GroupSplit& sp) {
   if constexpr (E::kCheapTotal) {
     return cheap_group_totals(ev, s, lo, len, sp);
+  } else if constexpr (E::kRawWeights) {
+    // Four 16-byte loads per lane issued together (the scheduler, near the
+    // register limit, would otherwise wait on each in turn): rows read from
+    // cache, such as a hub every walk starts from, are bound by load latency.
+    const int lane = lane_id();
+    uint64_t mine = 0;
+    for (uint32_t g = 0; g < sp.groups; ++g) {
+      const uint32_t gb = lo + g * sp.gsz;
+      const uint32_t ge = min(gb + sp.gsz, lo + len);
+      uint64_t acc = 0;
+      uint32_t q = gb + lane;
+#pragma unroll 1
+      for (; q + 3 * kWave < ge; q += 4 * kWave) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = ev.quad_raw(q + k * kWave);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += raw_quad_sum(s, q + k * kWave, v[k]);
+      }
+      if (q + kWave < ge) {
+        const uint4 a = ev.quad_raw(q), b = ev.quad_raw(q + kWave);
+        __builtin_amdgcn_sched_barrier(0);
+        acc += raw_quad_sum(s, q, a) + raw_quad_sum(s, q + kWave, b);
+        q += 2 * kWave;
+      }
+      if (q < ge) acc += raw_quad_sum(s, q, ev.quad_raw(q));
+      const uint64_t tot = wave_sum(acc);
+      if ((uint32_t)lane == g) mine = tot;
+    }
+    return mine;
   } else {
     const int lane = lane_id();
     uint64_t mine = 0;
