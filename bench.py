@@ -200,25 +200,42 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
 
 
 def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
-                budget: int, log):
+                budget: int, log, mix: str = "mixed", graph=None):
     """Poisson request streams against the served form, one per offered rate
     (each for `seconds`, capped at `max_requests` requests); returns latency
     and throughput per rate.  Latency = completion (server clock) minus the
-    request's scheduled arrival time (both CLOCK_MONOTONIC)."""
+    request's scheduled arrival time (both CLOCK_MONOTONIC).  mix "mixed":
+    DeepWalk, node2vec and MetaPath requests of lengths U{10..80}; "recipe":
+    every request is the workload's own walk.  graph = (host graph, uploaded
+    handle) of the same workload, reused instead of generated again."""
     import threading
-    g = synth.load_recipe_graph(workload)
-    G = fw.Graph.of(g)
-    params = [(("deepwalk"), None),
-              ("node2vec", fw.make_params(fw.node2vec_factors(2, 1, 1, 2))),
-              ("metapath", fw.make_params(schema=[0, 1, 2]))]
+    if graph is None:
+        g = synth.load_recipe_graph(workload)
+        G = fw.Graph.of(g)
+    else:
+        g, G = graph
+    if mix == "recipe":
+        r_algo, r_prm, r_walk = recipe_params(fw, synth.RECIPES[workload])
+        params = [(r_algo, r_prm)]
+        mix_text = (f"sizes floor(log-uniform[1,65536]), every request the workload's "
+                    f"{r_algo} walk of length {r_walk['length']}, Poisson arrivals")
+    else:
+        params = [(("deepwalk"), None),
+                  ("node2vec", fw.make_params(fw.node2vec_factors(2, 1, 1, 2))),
+                  ("metapath", fw.make_params(schema=[0, 1, 2]))]
+        mix_text = ("sizes floor(log-uniform[1,65536]), algorithm uniform over "
+                    "{DeepWalk, node2vec p=2 q=1/2, MetaPath [0,1,2]}, length U{10..80}, "
+                    "Poisson arrivals")
     out = []
     for k, rate in enumerate(rates):
         rng = np.random.default_rng(2024 + k)
         n_req = max(1, min(max_requests, int(seconds * rate)))
         arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
         sizes = np.floor(np.exp(rng.uniform(0, np.log(65536), n_req))).astype(np.int64)
-        kinds = rng.integers(0, 3, n_req)
+        kinds = rng.integers(0, len(params), n_req)
         lengths = rng.integers(10, 81, n_req)
+        if mix == "recipe":
+            lengths[:] = r_walk["length"]
         seeds = rng.integers(0, 1 << 62, n_req)
         starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77 + k)
         offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -264,13 +281,12 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
                  keeps_up=bool(wall <= 1.1 * span + 0.5))
         log(f"serve @ {rate}/s: {r}")
         out.append(r)
-    G.free()
+    if graph is None:
+        G.free()
     kept = [r for r in out if r["keeps_up"]]
     head = max(kept, key=lambda r: r["offered_rate_per_s"]) if kept else out[0]
     return dict(workload=workload, mem_budget_bytes=budget,
-                request_mix="sizes floor(log-uniform[1,65536]), algorithm uniform over "
-                            "{DeepWalk, node2vec p=2 q=1/2, MetaPath [0,1,2]}, length U{10..80}, "
-                            "Poisson arrivals",
+                request_mix=mix_text,
                 p50_ms=head["p50_ms"], p99_ms=head["p99_ms"],
                 at_rate_per_s=head["offered_rate_per_s"],
                 note="p50/p99 at the highest offered rate the server kept up with",
@@ -381,6 +397,9 @@ def main():
                     help="offered request rates (requests/s), comma-separated")
     ap.add_argument("--serve-max-requests", type=int, default=3000)
     ap.add_argument("--serve-workload", default="rmat24_serve")
+    ap.add_argument("--serve-mix", default="mixed", choices=["mixed", "recipe"],
+                    help="mixed: DeepWalk / node2vec / MetaPath requests; recipe: every "
+                         "request is the serve workload's own walk")
     ap.add_argument("--queries", type=int, default=0,
                     help="time only the first N queries of the workload (0 = all)")
     ap.add_argument("--host-batches", type=int, default=0,
@@ -534,8 +553,9 @@ def main():
         del out
         torch.cuda.empty_cache()
         rates = [float(x) for x in args.serve_rates.split(",") if x]
+        same = (g, G) if args.serve_workload == args.workload else None
         latency = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
-                              args.serve_max_requests, 4 << 30, log)
+                              args.serve_max_requests, 4 << 30, log, args.serve_mix, same)
 
     res = {
         "metric": METRIC,
