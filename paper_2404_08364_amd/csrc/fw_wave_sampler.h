@@ -13,10 +13,14 @@
 // level re-reads 1/64 of the previous one.
 //
 // Quad indices are 32-bit (slices are shorter than 2^28 entries) and every
-// load is addressed from the slice's uniform base.  The transition-weight
-// evaluator is inlined at exactly two places (the streaming loop and the last
-// level): the walkers' instruction footprint has to stay inside the
-// instruction cache.
+// load is addressed from the slice's uniform base.  The full transition-weight
+// evaluator is inlined at most twice (the streaming pass and the last level;
+// the streaming passes of unweighted MetaPath and of weighted DeepWalk / PPR
+// use small dedicated forms instead): the walkers' instruction footprint has
+// to stay inside the instruction cache.  Where a streaming pass issues
+// several loads per lane, a scheduling barrier keeps them together: near the
+// register limit of eight wavefronts per SIMD the compiler otherwise waits on
+// each load before issuing the next.
 #pragma once
 
 #include "fw_device.h"
