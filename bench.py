@@ -434,8 +434,9 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(queries shard trivially across GPUs, see the design notes)"}))
+        print(json.dumps({"error": "the walker runs on one GPU per process; --gpus must be 1 "
+                                   "(queries are independent and keyed by their global id: "
+                                   "split the query range across GPUs)"}))
         sys.exit(2)
 
     import torch
