@@ -200,7 +200,7 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
 
 
 def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
-                budget: int, log, mix: str = "mixed", graph=None):
+                budget: int, log, mix: str = "mixed", graph=None, inflight: int = 4):
     """Poisson request streams against the served form, one per offered rate
     (each for `seconds`, capped at `max_requests` requests); returns latency
     and throughput per rate.  Latency = completion (server clock) minus the
@@ -239,7 +239,8 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
         seeds = rng.integers(0, 1 << 62, n_req)
         starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77 + k)
         offs = np.concatenate([[0], np.cumsum(sizes)])
-        srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=4, max_batch_requests=512)
+        srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=inflight,
+                        max_batch_requests=512)
         tickets = [None] * n_req
         sched_ns = [0] * n_req
         lat = np.zeros(n_req)
@@ -397,6 +398,8 @@ def main():
                     help="offered request rates (requests/s), comma-separated")
     ap.add_argument("--serve-max-requests", type=int, default=3000)
     ap.add_argument("--serve-workload", default="rmat24_serve")
+    ap.add_argument("--serve-inflight", type=int, default=4,
+                    help="batches the server keeps on the GPU at once (1..16)")
     ap.add_argument("--serve-mix", default="mixed", choices=["mixed", "recipe"],
                     help="mixed: DeepWalk / node2vec / MetaPath requests; recipe: every "
                          "request is the serve workload's own walk")
@@ -556,7 +559,8 @@ def main():
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         same = (g, G) if args.serve_workload == args.workload else None
         latency = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
-                              args.serve_max_requests, 4 << 30, log, args.serve_mix, same)
+                              args.serve_max_requests, 4 << 30, log, args.serve_mix, same,
+                              args.serve_inflight)
 
     res = {
         "metric": METRIC,
