@@ -253,7 +253,7 @@ int fw_walk_host(const fw_graph* g, fw_algo algo, const fw_params* params,
 int fw_count_steps(const uint32_t* out_paths, uint64_t n, uint32_t length, void* stream,
                    uint64_t* steps);
 
-/* Sampler microbenchmark (the comparison of sampling methods, section 6.5,
+/* Sampler microbenchmark (the comparison of sampling methods, section 6.3,
  * and of rejection sampling, Appendix C).  n_tasks independent tasks; task j
  * picks one index i of the weights w = weights[j * size .. (j + 1) * size)
  * with chance w_i / T, T = sum(w), and writes it to picks[j] (FW_END when

@@ -128,7 +128,7 @@ void fwo_zigzag_order(uint64_t d, uint32_t k, uint64_t* order);
  * the last selected entry, or -1 when every weight is 0. */
 int64_t fwo_reservoir(const uint64_t* w, const uint64_t* u, const uint64_t* order, uint64_t d);
 
-/* Sampler microbenchmark tasks (section 6.5's comparison of sampling
+/* Sampler microbenchmark tasks (section 6.3's comparison of sampling
  * methods): task j picks one index of the `size` weights w[0 .. size) with
  * chance w_i / T, T = sum(w), or returns -1 when T = 0.  Draws are keyed by
  * (seed, task j):

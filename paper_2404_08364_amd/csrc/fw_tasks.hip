@@ -1,5 +1,5 @@
 // Sampler microbenchmark (the comparison of sampling methods in section
-// 6.5): n_tasks independent tasks, task j picking one index of the `size`
+// 6.3): n_tasks independent tasks, task j picking one index of the `size`
 // weights w[j*size, (j+1)*size) with chance w_i / T, one wavefront per task
 // (grid-stride).  The bufferless samplers (ITS, DPRS, ZPRS) are the walkers'
 // own; the buffered ones keep O(size) state per task in a device scratch

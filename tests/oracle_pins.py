@@ -177,6 +177,47 @@ def pin_walk_rebuilt():
             assert rows[i].tolist() == exp, (algo, i, rows[i], exp)
 
 
+
+def pin_walk_ids_rebuilt():
+    """Walks of a chosen list of query ids (the form behind every sampled
+    parity check and the CPU baseline): row j is the walk of query qids[j]
+    from starts[qids[j]], keyed by that id, rebuilt from independent parts,
+    for a shuffled, non-contiguous id list whose start vertices differ from
+    the ids; the threaded form returns the same rows in the same order."""
+    from helpers import hop_distances
+    g, _ = tiny6()
+    dist = hop_distances(g)
+    seed, L, n = 987654321, 5, 90
+    starts = ((np.arange(n) * 5 + 3) % 6).astype(np.uint32)
+    qids = np.random.default_rng(4).permutation(n)[:30].astype(np.uint64)
+    for algo, f, sch in [("deepwalk", (1, 1, 1), ()), ("node2vec", (1, 2, 4), ()),
+                         ("metapath", (1, 1, 1), (1, 0))]:
+        prm = oracle.params(*f, schema=sch)
+        rows = oracle.walk_ids(g, algo, prm, starts, qids, L, seed)
+        for j, q in enumerate(qids):
+            exp = _python_walk(g, dist, algo, int(starts[q]), int(q), L, seed, f, sch)
+            assert rows[j].tolist() == exp, (algo, j, int(q), rows[j], exp)
+        thr = oracle.walk_ids_threaded(g, algo, prm, starts, qids, L, seed, 4)
+        assert np.array_equal(thr, rows), algo
+
+
+def pin_walk_ids_rmat12():
+    """On R-MAT-12 (node2vec p=2 q=1/2, 20 hops) the rows of a shuffled id
+    list equal the same rows of the whole query set, single-threaded and
+    threaded."""
+    import synth
+    g = synth.load_recipe_graph("rmat12_n2v", use_cache=False)
+    n = g.n_vertices
+    starts = ((np.arange(n, dtype=np.uint64) * 2654435761) % n).astype(np.uint32)
+    prm = oracle.params(1, 2, 4)
+    full = oracle.walk(g, "node2vec", prm, starts, 20, 42)
+    qids = np.random.default_rng(8).permutation(n)[:700].astype(np.uint64)
+    rows = oracle.walk_ids(g, "node2vec", prm, starts, qids, 20, 42)
+    assert np.array_equal(rows, full[qids.astype(np.int64)])
+    thr = oracle.walk_ids_threaded(g, "node2vec", prm, starts, qids, 20, 42, 8)
+    assert np.array_equal(thr, rows)
+
+
 def pin_identities():
     """node2vec with equal factors is DeepWalk; MetaPath whose schema matches
     every label is unit-weight DeepWalk; both bit-exact."""
@@ -635,7 +676,8 @@ def pin_task_samplers_rebuilt():
 
 
 ALL_PINS = [pin_philox_kat, pin_philox_numpy, pin_draw_keying, pin_scale_closed_form,
-            pin_pick_bruteforce, pin_hand_weights, pin_walk_rebuilt, pin_chi2_paths, pin_identities,
+            pin_pick_bruteforce, pin_hand_weights, pin_walk_rebuilt, pin_walk_ids_rebuilt,
+            pin_walk_ids_rmat12, pin_chi2_paths, pin_identities,
             pin_regular_uniform, pin_path_graph_edges, pin_errors,
             pin_zero_length_and_dead_ends, pin_stop_coin_closed_form, pin_stop_keying,
             pin_ppr_rebuilt, pin_ppr_length_distribution, pin_ppr_limits,

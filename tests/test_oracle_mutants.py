@@ -42,6 +42,8 @@ MUTANTS = {
     "alias_accept_le": ("pick = mulhi64(out[1], T) < prob[c]", "pick = mulhi64(out[1], T) <= prob[c]"),
     "rjs_accept_le": ("if (mulhi64(out[1], wmax) < w[c]) return", "if (mulhi64(out[1], wmax) <= w[c]) return"),
     "rjs_trial_key": ("uint64_t ctr[4] = {task, k, 0, 3};", "uint64_t ctr[4] = {task, 0, k, 3};"),
+    "walk_ids_key": ("starts[qids[j]], qids[j], length", "starts[qids[j]], j, length"),
+    "walk_ids_start": ("FWO_SAMPLER_ITS, starts[qids[j]], qids[j]", "FWO_SAMPLER_ITS, starts[j], qids[j]"),
     "padding": ("for (uint32_t s = t + 1; s <= length; ++s)", "for (uint32_t s = t + 1; s < length; ++s)"),
 }
 
