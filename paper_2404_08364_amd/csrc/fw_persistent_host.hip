@@ -28,9 +28,30 @@ struct GraphKey {
   bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) < 0; }
 };
 
-struct GraphCache {
-  std::map<GraphKey, std::pair<hipGraphExec_t, uint64_t*>> execs;
+// A captured launch: its executable graph and the task-pool head counter it
+// owns (captured into the graph, so no other launch ever uses it).
+struct CachedExec {
+  hipGraphExec_t exec = nullptr;
+  uint64_t* head = nullptr;
+  uint64_t last_use = 0;
 };
+
+// Captured launches of one graph handle, at most kMaxCachedExecs of them; the
+// least recently replayed one is dropped first (after its stream drains).
+constexpr size_t kMaxCachedExecs = 16;
+
+struct GraphCache {
+  std::map<GraphKey, CachedExec> execs;
+  uint64_t clock = 0;
+};
+
+void drop_exec(const GraphKey& key, CachedExec& c) {
+  (void)hipStreamSynchronize(key.stream);  // a replay may still be running
+  (void)hipGraphExecDestroy(c.exec);
+  (void)hipFree(c.head);
+  c.exec = nullptr;
+  c.head = nullptr;
+}
 
 }  // namespace
 
@@ -123,23 +144,38 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
   auto* cache = static_cast<GraphCache*>(g->graph_cache);
   auto it = cache->execs.find(key);
   if (it == cache->execs.end()) {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    const hipError_t le = launch(a, stream);
-    e = hipStreamEndCapture(stream, &graph);
-    if (le != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return le;
+    if (cache->execs.size() >= kMaxCachedExecs) {
+      auto lru = cache->execs.begin();
+      for (auto j = cache->execs.begin(); j != cache->execs.end(); ++j)
+        if (j->second.last_use < lru->second.last_use) lru = j;
+      drop_exec(lru->first, lru->second);
+      cache->execs.erase(lru);
     }
+    // The captured launch resets and claims from a counter of its own: a
+    // rotated head slot could be handed to an eager launch running on another
+    // stream at the same time as a replay.
+    CachedExec c;
+    hipError_t e = hipMalloc((void**)&c.head, kHeadStride * sizeof(uint64_t));
     if (e != hipSuccess) return e;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return e;
-    it = cache->execs.emplace(key, std::make_pair(exec, a.head)).first;
+    LaunchArgs x = a;
+    x.head = c.head;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t le = launch(x, stream);
+      e = hipStreamEndCapture(stream, &graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      (void)hipFree(c.head);
+      return e;
+    }
+    it = cache->execs.emplace(key, c).first;
   }
-  return hipGraphLaunch(it->second.first, stream);
+  it->second.last_use = ++cache->clock;
+  return hipGraphLaunch(it->second.exec, stream);
 }
 
 // Times cfg on the sample: a warm-up launch, then the faster of two timed
@@ -243,7 +279,7 @@ int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts,
 void release_graph_state(fw_graph* g) {
   auto* cache = static_cast<GraphCache*>(g->graph_cache);
   if (!cache) return;
-  for (auto& kv : cache->execs) (void)hipGraphExecDestroy(kv.second.first);
+  for (auto& kv : cache->execs) drop_exec(kv.first, kv.second);
   delete cache;
   g->graph_cache = nullptr;
 }

@@ -70,8 +70,11 @@ def test_rmat22_node2vec_full_size(mode):
     _run("rmat22_n2v", mode, 65536, 1024)
 
 
-def test_rmat22_deepwalk_full_size():
-    _run("rmat22_deepwalk", "persistent", 65536, 1024)
+@pytest.mark.parametrize("mode", ["persistent", "plain"])
+def test_rmat22_deepwalk_full_size(mode):
+    """Weighted DeepWalk on the same graph, all 4,194,304 queries, 80 hops,
+    in the persistent and the plain batch walker."""
+    _run("rmat22_deepwalk", mode, 65536, 1024)
 
 
 def test_chunglu24_metapath_full_size():

@@ -68,6 +68,46 @@ def test_star_hub_degrees(env, mode, d):
         _check(env, g, algo, f, sch, starts, 9, 1234, mode)
 
 
+def _big_star(d, seed):
+    """Star of d leaves built with numpy (vertex 0 is the hub).  The last
+    fiftieth of the hub's row carries about half of its weight, so draws land
+    in the tail groups of the multi-level locate as often as elsewhere."""
+    rng = np.random.default_rng(seed)
+    w = rng.integers(1, 1000, d).astype(np.uint32)
+    tail = d - d // 50
+    w[tail:] = rng.integers(20_000, 29_000, d - tail)
+    lab = rng.integers(0, 3, d).astype(np.uint8)
+    from types import SimpleNamespace
+    off = np.concatenate([[0], d + np.arange(0, d + 1)]).astype(np.uint64)
+    adj = np.concatenate([np.arange(1, d + 1), np.zeros(d)]).astype(np.uint32)
+    return SimpleNamespace(offsets=off, adj=adj, weights=np.concatenate([w, w]),
+                           labels=np.concatenate([lab, lab]), n_vertices=d + 1,
+                           n_edges=2 * d)
+
+
+_BIG_STAR_ALGOS = [("deepwalk", (1, 1, 1), (), (0, 1)), ("node2vec", (2, 3, 5), (), (0, 1)),
+                   ("metapath", (1, 1, 1), (1, 2), (0, 1)), ("ppr", (1, 1, 1), (), (1, 5))]
+
+
+@pytest.mark.parametrize("d", [1_048_577, 2_840_149])
+def test_star_hub_three_level_locate(env, d):
+    """Hubs of more than 2^20 entries: the locate descends three levels of
+    64 groups before the last 64 quads (rows of the largest synthetic
+    graph reach 2,840,149 entries).  Every algorithm, every mode."""
+    torch, fw = env
+    g = _big_star(d, d)
+    G = fw.Graph.of(g)
+    starts = np.concatenate([np.zeros(24, np.uint32), np.arange(1, 25, dtype=np.uint32),
+                             np.array([d, d - 1, d // 2], np.uint32)])
+    for algo, f, sch, stop in _BIG_STAR_ALGOS:
+        exp = oracle.walk(g, algo, oracle.params(*f, schema=sch, stop=stop), starts, 6, 4321)
+        prm = fw.make_params(f, sch, stop)
+        for mode in MODES:
+            got = gpu_walk(torch, fw, G, algo, prm, starts, 6, 4321, mode)
+            assert_rows_equal(got, exp, f"{algo} {mode} d={d}")
+    G.free()
+
+
 @pytest.fixture(scope="module")
 def powerlaw():
     g = synth.chung_lu(20_000, 300_000, 2.1, 1.5, seed=5)
@@ -393,6 +433,64 @@ def test_graph_replay_matches_eager(env, powerlaw):
         del junk
     exp = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts.cpu().numpy(), 15, 77)
     assert_rows_equal(out.cpu().numpy().view(np.uint32), exp, "graph replay")
+
+
+def test_graph_replay_beside_eager_walks(env, powerlaw):
+    """A captured walk replayed on one stream while more eager persistent
+    walks than there are rotating head slots (64) run on another stream: the
+    captured launch claims queries from a counter of its own, so no query of
+    either side is skipped or walked twice."""
+    torch, fw = env
+    g = powerlaw
+    G = fw.Graph.of(g)
+    prm = fw.make_params((1, 2, 4))
+    starts = torch.arange(0, g.n_vertices, 2, dtype=torch.int32, device="cuda")
+    small = starts[:777].contiguous()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    out_a = torch.empty((starts.numel(), 13), dtype=torch.int32, device="cuda")
+    outs_b = [torch.empty((small.numel(), 6), dtype=torch.int32, device="cuda")
+              for _ in range(70)]
+    exp_a = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts.cpu().numpy(), 12, 5)
+    small_np = small.cpu().numpy()
+    exp_b = [oracle.walk(g, "deepwalk", oracle.params(), small_np, 5, 1000 + i)
+             for i in range(len(outs_b))]
+    for rep in range(3):
+        out_a.fill_(-7)
+        for ob in outs_b:
+            ob.fill_(-7)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(sa):
+            fw.walk(G, "node2vec", prm, starts, 12, 5, out=out_a, mode="persistent",
+                    stream=sa, async_=True, use_graph=True)
+        with torch.cuda.stream(sb):
+            for i, ob in enumerate(outs_b):
+                fw.walk(G, "deepwalk", None, small, 5, 1000 + i, out=ob, mode="persistent",
+                        stream=sb, async_=True)
+        fw.sync(G, sa)
+        fw.sync(G, sb)
+        assert_rows_equal(out_a.cpu().numpy().view(np.uint32), exp_a, f"replay {rep}")
+        for i, ob in enumerate(outs_b):
+            assert_rows_equal(ob.cpu().numpy().view(np.uint32), exp_b[i], f"eager {i} rep {rep}")
+
+
+def test_graph_cache_is_bounded(env, powerlaw):
+    """Replays keyed by many seeds (more than the cache holds) stay correct:
+    old captured launches are dropped, the latest ones replay."""
+    torch, fw = env
+    g = powerlaw
+    G = fw.Graph.of(g)
+    starts = torch.arange(0, g.n_vertices, 37, dtype=torch.int32, device="cuda")
+    st_np = starts.cpu().numpy()
+    s = torch.cuda.Stream()
+    out = torch.empty((starts.numel(), 8), dtype=torch.int32, device="cuda")
+    for seed in list(range(40)) + [39, 38, 0]:
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            fw.walk(G, "deepwalk", None, starts, 7, seed, out=out, mode="persistent",
+                    stream=s, use_graph=True)
+        exp = oracle.walk(g, "deepwalk", oracle.params(), st_np, 7, seed)
+        assert_rows_equal(out.cpu().numpy().view(np.uint32), exp, f"seed {seed}")
 
 
 def test_async_on_stream_and_qid_base(env, powerlaw):
