@@ -214,15 +214,22 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
 
 
 def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
-                budget: int, log, mix: str = "mixed", graph=None, inflight: int = 4):
+                budget: int, log, mix: str = "mixed", graph=None, inflight: int = 4,
+                ceiling_requests: int = 4000, check_every: int = 64):
     """Poisson request streams against the served form, one per offered rate
-    (each for `seconds`, capped at `max_requests` requests); returns latency
-    and throughput per rate.  Latency = completion (server clock) minus the
-    request's scheduled arrival time (both CLOCK_MONOTONIC).  mix "mixed":
+    (each for `seconds` of arrivals, capped at `max_requests` requests);
+    returns latency and throughput per rate, and the served form's ceiling
+    on the same mix: `ceiling_requests` requests submitted at once, steps /
+    makespan.  Latency = completion (server clock) minus the request's
+    scheduled arrival time (both CLOCK_MONOTONIC); steps are the realised
+    hops the device counted per request.  Every `check_every`-th request's
+    rows are compared with the batch walker's rows for the same starts and
+    seed (a request's walks are the same alone and in the mix).  mix "mixed":
     DeepWalk, node2vec and MetaPath requests of lengths U{10..80}; "recipe":
     every request is the workload's own walk.  graph = (host graph, uploaded
     handle) of the same workload, reused instead of generated again."""
     import threading
+    import torch
     if graph is None:
         g = synth.load_recipe_graph(workload)
         G = fw.Graph.of(g)
@@ -240,11 +247,11 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
         mix_text = ("sizes floor(log-uniform[1,65536]), algorithm uniform over "
                     "{DeepWalk, node2vec p=2 q=1/2, MetaPath [0,1,2]}, length U{10..80}, "
                     "Poisson arrivals")
-    out = []
-    for k, rate in enumerate(rates):
+
+    def stream(k, rate, n_req):
         rng = np.random.default_rng(2024 + k)
-        n_req = max(1, min(max_requests, int(seconds * rate)))
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        arrivals = (np.cumsum(rng.exponential(1.0 / rate, n_req)) if rate > 0
+                    else np.zeros(n_req))
         sizes = np.floor(np.exp(rng.uniform(0, np.log(65536), n_req))).astype(np.int64)
         kinds = rng.integers(0, len(params), n_req)
         lengths = rng.integers(10, 81, n_req)
@@ -259,6 +266,7 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
         sched_ns = [0] * n_req
         lat = np.zeros(n_req)
         hops = np.zeros(n_req, dtype=np.int64)
+        kept = {}
 
         def submitter(t0):
             for i in range(n_req):
@@ -278,22 +286,48 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
         while done < n_req:
             while tickets[done] is None:
                 time.sleep(0.0005)
-            paths, st = srv.wait(tickets[done])
+            keep = check_every > 0 and done % check_every == 0
+            paths, st = srv.wait(tickets[done], rows=keep)
             lat[done] = (st["done_ns"] - sched_ns[done]) / 1e6
-            hops[done] = int((paths[:, 1:] != 0xFFFFFFFF).sum())
+            hops[done] = int(st["steps"])
+            if keep:
+                kept[done] = paths
             done += 1
         th.join()
         t_end = time.monotonic_ns()
         srv.close()
+        # The kept requests again, alone, through the batch walker.
+        same = True
+        for i, paths in kept.items():
+            algo, prm = params[kinds[i]]
+            st_dev = torch.from_numpy(starts_all[offs[i]:offs[i + 1]].view(np.int32)).cuda()
+            alone = fw.walk(G, algo, prm, st_dev, int(lengths[i]), int(seeds[i]),
+                            mode="persistent")
+            torch.cuda.synchronize()
+            same &= bool(np.array_equal(alone.cpu().numpy().view(np.uint32), paths))
+            same &= int(hops[i]) == int((paths[:, 1:] != 0xFFFFFFFF).sum())
         wall = (t_end - t0) / 1e9
         span = float(arrivals[-1])
         offered = float(hops.sum()) / span if span > 0 else float("nan")
         served = float(hops.sum()) / wall
-        r = dict(offered_rate_per_s=rate, requests=n_req, arrival_span_s=span, duration_s=wall,
-                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                 mean_ms=float(lat.mean()), offered_steps_per_s=offered,
-                 served_steps_per_s=served, served_queries=int(sizes.sum()),
-                 keeps_up=bool(wall <= 1.1 * span + 0.5))
+        return dict(offered_rate_per_s=rate if rate > 0 else None, requests=n_req,
+                    arrival_span_s=span, duration_s=wall,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    mean_ms=float(lat.mean()), offered_steps_per_s=offered,
+                    served_steps_per_s=served, served_queries=int(sizes.sum()),
+                    steps=int(hops.sum()), keeps_up=bool(wall <= 1.1 * span + 0.5),
+                    rows_checked=len(kept), rows_match_alone=same)
+
+    ceiling = None
+    if ceiling_requests > 0:
+        ceiling = stream(999, 0.0, ceiling_requests)
+        log(f"serve ceiling (all {ceiling_requests} requests at once): {ceiling}")
+    out = []
+    for k, rate in enumerate(rates):
+        n_req = max(1, min(max_requests, int(seconds * rate)))
+        r = stream(k, rate, n_req)
+        if ceiling:
+            r["served_over_ceiling"] = r["served_steps_per_s"] / ceiling["served_steps_per_s"]
         log(f"serve @ {rate}/s: {r}")
         out.append(r)
     if graph is None:
@@ -305,7 +339,7 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
                 p50_ms=head["p50_ms"], p99_ms=head["p99_ms"],
                 at_rate_per_s=head["offered_rate_per_s"],
                 note="p50/p99 at the highest offered rate the server kept up with",
-                sweep=out)
+                ceiling=ceiling, sweep=out)
 
 
 def sampler_sweep():
@@ -398,6 +432,9 @@ def main():
     ap.add_argument("--workload", default="rmat22_n2v", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="persistent", choices=["plain", "persistent", "auto"])
     ap.add_argument("--compare-plain", type=int, default=1)
+    ap.add_argument("--plain-slices", type=int, default=1,
+                    help="run the plain comparison as this many launches over consecutive "
+                         "query ranges (same rows), logging each")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--use-graph", type=int, default=1)
@@ -406,11 +443,14 @@ def main():
                     help="queries the autotuner times (0 = every k-th query, at least "
                          "65536 and 1/64 of the workload, so that the sample's few long "
                          "walks do not decide the timings)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="seconds of arrivals per offered rate (0 = no serve phase)")
-    ap.add_argument("--serve-rates", default="50,100,250,500,1000,2000",
+    ap.add_argument("--serve-rates", default="250,500,1000,2000",
                     help="offered request rates (requests/s), comma-separated")
-    ap.add_argument("--serve-max-requests", type=int, default=3000)
+    ap.add_argument("--serve-max-requests", type=int, default=100000)
+    ap.add_argument("--serve-ceiling", type=int, default=4000,
+                    help="requests submitted at once to measure the served form's ceiling "
+                         "on the same mix (0 = skip)")
     ap.add_argument("--serve-workload", default="rmat24_serve")
     ap.add_argument("--serve-inflight", type=int, default=4,
                     help="batches the server keeps on the GPU at once (1..16)")
@@ -525,7 +565,30 @@ def main():
         f"-> {value / 1e6:.1f} M steps/s, {achieved:.0f} GB/s algorithmic")
 
     plain = None
-    if args.compare_plain and args.mode != "plain":
+    if args.compare_plain and args.mode != "plain" and args.plain_slices > 1:
+        # The plain walker over consecutive slices of the query set (query ids
+        # kept by qid_base, so the rows are those of one launch), one launch
+        # and one log line per slice.
+        out.fill_(-7)
+        bounds = np.linspace(0, n, args.plain_slices + 1).astype(np.int64)
+        total_ms = 0.0
+        for k in range(args.plain_slices):
+            lo, hi = int(bounds[k]), int(bounds[k + 1])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fw.walk(G, algo, prm, starts[lo:hi], L, seed, out=out[lo:hi], mode="plain",
+                    stream=stream, async_=True, qid_base=lo)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            fw.sync(G, stream)
+            total_ms += e0.elapsed_time(e1)
+            log(f"plain slice {k + 1}/{args.plain_slices}: queries {lo}..{hi}, "
+                f"{e0.elapsed_time(e1):.1f} ms")
+        same = bool(torch.equal(out, paths_main))
+        plain = dict(ms_per_step=total_ms, value=hops / (total_ms / 1e3), identical_paths=same,
+                     slices=args.plain_slices)
+        log(f"plain: {total_ms:.1f} ms in {args.plain_slices} slices, identical={same}")
+    elif args.compare_plain and args.mode != "plain":
         ms_p, kern_p, _ = timed("plain", max(1, min(args.steps, 2)), 0)
         same = bool(torch.equal(out, paths_main))
         plain = dict(ms_per_step=ms_p, value=hops / (ms_p / 1e3), identical_paths=same)
@@ -580,7 +643,7 @@ def main():
         same = (g, G) if args.serve_workload == args.workload else None
         latency = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
                               args.serve_max_requests, 4 << 30, log, args.serve_mix, same,
-                              args.serve_inflight)
+                              args.serve_inflight, args.serve_ceiling)
 
     res = {
         "metric": METRIC,

@@ -167,6 +167,15 @@ typedef struct fw_tune {
   uint32_t wgs_per_cu;   /* resident workgroups per compute unit */
   uint32_t fetch;        /* reserved, 0 */
   uint32_t hash_cells;   /* LDS cells for the node2vec membership structure */
+  uint32_t mode;         /* fw_autotune's output: the form FW_MODE_AUTO runs,
+                            FW_MODE_PERSISTENT or FW_MODE_STAGED (ignored as
+                            input) */
+  uint32_t sparse_ratio; /* persistent node2vec: a hop whose degree is at
+                            least 2048 and at least sparse_ratio times
+                            d(prev) computes its total from the raw weights
+                            and looks N(prev)'s ids up in N(cur), instead of
+                            testing every entry of N(cur) against N(prev)
+                            (0 = tuned/default 64, 0xFFFFFFFF = never) */
 } fw_tune;
 
 /* How each hop picks its neighbour (fw_walk_opts.sampler).
@@ -203,14 +212,22 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
                const uint32_t* starts, uint64_t n, uint32_t length, uint64_t seed,
                uint32_t* out_paths, const fw_walk_opts* opts);
 
-/* Autotuner for the persistent form (the hyper-parameter study of Appendix
- * C.2, run on the target GPU): times candidate configurations (resident
- * workgroups per CU, node2vec membership-table size, tiny-degree threshold)
- * on the n queries of `starts` (device, a sample of the real query set),
- * keeps the fastest as the graph's configuration for `algo` (used by later
- * FW_MODE_AUTO / FW_MODE_PERSISTENT walks and servers created afterwards
- * that pass no explicit fw_tune) and copies it to *best (may be NULL).  Runs
- * on `stream` and blocks; allocates a temporary n * (length + 1) output.
+/* Autotuner (the hyper-parameter study of Appendix C.2, run on the target
+ * GPU): times candidate configurations on the n queries of `starts`
+ * (device, a sample of the real query set):
+ *   persistent form: resident workgroups per CU, node2vec membership-table
+ *     size, then the tiny-degree threshold (coordinate search);
+ *   staged form (the paper's block design): threads per workgroup
+ *     (256/512/1024), hub threshold d_t (1024/4096/16384) and local pool
+ *     size |P_L| (32/64).
+ * The fastest of each form is kept for the graph and `algo`, keyed by the
+ * graph's fingerprint (sizes, degree and weight maxima, and sampled offsets,
+ * ids, weights and labels) and device, so a re-upload of the same graph
+ * finds it; FW_MODE_AUTO runs the faster form, FW_MODE_PERSISTENT and
+ * FW_MODE_STAGED their own tuned configuration (walks and servers created
+ * afterwards that pass no explicit fw_tune).  The winner is copied to *best
+ * (may be NULL; best->mode names its form).  Runs on `stream` and blocks;
+ * allocates a temporary n * (length + 1) output.
  * Errors: as fw_walk, FW_ENOMEM. */
 int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32_t* starts,
                 uint64_t n, uint32_t length, uint64_t seed, void* stream, fw_tune* best);
@@ -324,6 +341,8 @@ typedef struct fw_req_stats {
   uint64_t n;
   uint32_t length;
   int status;
+  uint64_t steps; /* realised hops of the request's walks (Alg. 1: one per
+                     appended vertex), counted on the device */
 } fw_req_stats;
 
 /* Creates a server for graph g (which must outlive it): allocates the device
@@ -346,7 +365,10 @@ int fw_server_poll(fw_server* s, uint64_t ticket);
 /* Blocks until the request finishes, copies its n * (length + 1) path
  * entries to out_host (host, may be NULL), fills *stats (may be NULL), and
  * releases the request and its memory.  Returns the request's status
- * (FW_ECANCELED if the server shut down first). */
+ * (FW_ECANCELED if the server shut down first).  Requests may be waited for
+ * in any order: a finished request keeps its device region until it is
+ * collected, unless the next request in arrival order needs the memory, in
+ * which case its rows move to host memory (held until the wait). */
 int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_stats* stats);
 
 /* Stops admitting, cancels queued requests (FW_ECANCELED), waits for

@@ -18,6 +18,8 @@ struct TuneCfg {
   uint32_t hash_cells;  // LDS hash-set cells per workgroup (power of two)
   uint32_t narrow;      // set per launch: max weight * max factor < 2^24, so a
                         // weight times a factor is one 24-bit multiply
+  uint32_t sparse_ratio;  // persistent node2vec: a hop with d(cur) >= ratio *
+                          // d(prev) looks N(prev)'s keys up in N(cur) (0: never)
 };
 
 // max_w * max_f < 2^24: the product of a weight and a factor fits 32 bits
@@ -48,10 +50,12 @@ struct LaunchArgs {
 
 // One walk request of a multi-request launch (the served form): query i of
 // the request has id qid_base + i, starts at starts[i] and writes row i of
-// out (length + 1 entries).
+// out (length + 1 entries); the realised hops of its retired queries are
+// added to *steps (may be null).
 struct ReqDesc {
   const uint32_t* starts;
   uint32_t* out;
+  unsigned long long* steps;
   uint64_t n, seed, qid_base;
   uint32_t length, pad;
   DevParams prm;

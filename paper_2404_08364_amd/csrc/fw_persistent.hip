@@ -41,6 +41,9 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t u, uint32_t shift) {
   return (uint32_t)__umul24(u, kFib24) >> shift;
 }
 constexpr int kGroups = 4;  // queries per wavefront
+// Node2vec hops from vertices of at least this degree may take the
+// sparse-N(prev) pass (sparse_prev_group_totals).
+constexpr uint64_t kSparseMinDegree = 2048;
 constexpr int kGroupLanes = 16;
 constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
 
@@ -137,7 +140,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // Chooses (and for the hash set builds) the membership structure of N(prev)
 // for one node2vec hop from a vertex of degree d, with the wavefront's lanes.
 __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restrict__ adj,
-                                            uint64_t d, int lane) {
+                                            uint64_t d, int lane, bool allow_merge = true) {
   tb.kind = 0;
   // Past 16x, searching for the few keys reads less than the build or the
   // merge (16 against 8, 32 and 64 measured on R-MAT-22 node2vec).
@@ -145,7 +148,7 @@ __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restric
   if (2 * tb.pd > tb.cells) {
     // Too large for the hash set: merge the sorted rows (the region must
     // hold at least one 256-entry staging round).
-    if (tb.cells >= 4 * kWave) tb.kind = 2;
+    if (allow_merge && tb.cells >= 4 * kWave) tb.kind = 2;
     return;
   }
   // The table takes the whole region: a smaller N(prev) gets a lower load,
@@ -378,6 +381,104 @@ __device__ __forceinline__ uint64_t merge_group_totals(const E& ev, const QuadSl
   return mine;
 }
 
+// Lower bound of u in the sorted run row[0, n), n >= 1: the first index
+// whose entry is >= u (n if none).  One trip count for every lane (n is
+// wave-uniform), each probe a load from the run's uniform base.
+__device__ __forceinline__ uint32_t row_lower_bound(const uint32_t* __restrict__ row, uint32_t n,
+                                                    uint32_t u) {
+  uint32_t base = 0, len = n;
+  while (len > 1) {  // the lower bound is in [base, base + len]
+    const uint32_t half = len >> 1;
+    base = row_at(row, base + half) < u ? base + half : base;
+    len -= half;
+  }
+  return base + (row_at(row, base) < u ? 1u : 0u);
+}
+
+// Pass 1 of a node2vec hop whose N(prev) is much shorter than N(cur), by the
+// identity (Eq. 2, weights w_i over N(cur))
+//   T_g = f_out * sum_{i in g} w_i + (f_in - f_out) * sum_{i in g, u_i in N(prev), u_i != prev} w_i
+//                                  + (f_ret - f_out) * sum_{i in g, u_i = prev} w_i
+// for every group g of GroupSplit: the first sum streams the weights alone
+// (entry counts when the graph has none) and never reads N(cur)'s ids; the
+// other two look each distinct key of N(prev), and prev itself, up in N(cur)
+// by binary search and add the weights they find (all entries of a repeated
+// id) to their group in LDS.  Arithmetic is modulo 2^64, exact because every
+// T_g is below 2^64.  Lane g returns T_g.  Uses the wavefront's LDS region.
+template <class E>
+__device__ __forceinline__ uint64_t sparse_prev_group_totals(const E& ev, const QuadSlice& s,
+                                                             const GroupSplit& sp,
+                                                             const Table& tb, int lane) {
+  // Raw totals.
+  const char* __restrict__ wrun = reinterpret_cast<const char*>(ev.w + s.a);
+  auto quad_raw = [wrun](uint32_t q) { return *reinterpret_cast<const uint4*>(wrun + q * 16u); };
+  uint64_t raw = 0;
+  if (ev.w != nullptr) {
+    for (uint32_t g = 0; g < sp.groups; ++g) {
+      const uint32_t gb = g * sp.gsz;
+      const uint32_t ge = min(gb + sp.gsz, s.nq);
+      uint64_t acc = 0;
+      uint32_t q = gb + lane;
+#pragma unroll 1
+      for (; q + 3 * kWave < ge; q += 4 * kWave) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = quad_raw(q + k * kWave);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += raw_quad_sum(s, q + k * kWave, v[k]);
+      }
+#pragma unroll 1
+      for (; q < ge; q += kWave) acc += raw_quad_sum(s, q, quad_raw(q));
+      const uint64_t tot = wave_sum(acc);
+      if ((uint32_t)lane == g) raw = tot;
+    }
+  } else if ((uint32_t)lane < sp.groups) {
+    const uint32_t gb = (uint32_t)lane * sp.gsz;
+    const uint32_t ge = min(gb + sp.gsz, s.nq);
+    uint32_t cnt = 4 * (ge - gb);
+    if (gb == 0) cnt -= s.lead;
+    if (ge == s.nq) cnt -= 4 * s.nq - s.lead - s.d;
+    raw = cnt;
+  }
+  // Corrections, one 64-bit LDS cell per group.
+  unsigned long long* corr = reinterpret_cast<unsigned long long*>(fw_dyn_lds + tb.base);
+  corr[lane] = 0ull;
+  wave_sync_lds();
+  const uint32_t* __restrict__ crow = ev.adj + s.o;  // N(cur)
+  const uint32_t* __restrict__ prow = ev.adj + tb.po;  // N(prev)
+  const uint64_t d_in = (uint64_t)ev.f_in - (uint64_t)ev.f_out;
+  const uint64_t d_ret = (uint64_t)ev.f_ret - (uint64_t)ev.f_out;
+  const uint32_t gq = sp.gsz;
+  // Round c: lane k looks up entry c + k of N(prev).
+  for (uint64_t c = 0; c < tb.pd; c += kWave) {
+    const uint64_t i = c + (uint64_t)lane;
+    const uint32_t u = i < tb.pd ? prow[i] : 0u;
+    // Repeated ids count once; prev's own id is a return, not a neighbour.
+    const bool want = i < tb.pd && u != ev.prev && (i == 0 || prow[i - 1] != u);
+    if (!ballot(want)) continue;
+    uint32_t pos = row_lower_bound(crow, s.d, u);
+    if (want) {
+      for (; pos < s.d && row_at(crow, pos) == u; ++pos) {
+        const uint32_t wt = ev.w != nullptr ? ev.w[s.o + pos] : 1u;
+        atomicAdd(&corr[((s.lead + pos) >> 2) / gq], (unsigned long long)(d_in * wt));
+      }
+    }
+  }
+  // Entries equal to prev (the return).
+  if (lane == 0) {
+    for (uint32_t pos = row_lower_bound(crow, s.d, ev.prev);
+         pos < s.d && row_at(crow, pos) == ev.prev; ++pos) {
+      const uint32_t wt = ev.w != nullptr ? ev.w[s.o + pos] : 1u;
+      atomicAdd(&corr[((s.lead + pos) >> 2) / gq], (unsigned long long)(d_ret * wt));
+    }
+  }
+  wave_sync_lds();
+  const uint64_t mine = (uint64_t)ev.f_out * raw + (uint64_t)corr[lane];
+  wave_sync_lds();
+  return (uint32_t)lane < sp.groups ? mine : 0ull;
+}
+
 template <int ALGO, bool WEIGHTED, class MEM>
 __device__ __forceinline__ Eval<ALGO, WEIGHTED, MEM> base_eval(const DevGraph& g,
                                                               const DevParams& prm, uint64_t o,
@@ -429,6 +530,12 @@ struct Reqs {
   }
   __device__ __forceinline__ ReqDesc get(uint32_t r) const { return MULTI ? tab.reqs[r] : one; }
 };
+
+// Served form: a retired query adds its realised hops to its request's
+// counter (one atomic per query).
+__device__ __forceinline__ void count_steps(const ReqDesc& R, uint32_t hops) {
+  if (R.steps != nullptr && hops != 0) atomicAdd(R.steps, (unsigned long long)hops);
+}
 
 // Eight wavefronts per SIMD (64 VGPRs): the walk is bound by the latency of
 // dependent loads (offsets, then the slice, then the LDS membership probes),
@@ -537,13 +644,17 @@ k_walk_persistent(
         if (total == 0) {
           for (uint32_t p = s_t + 1 + gl; p <= length; p += kGroupLanes) row[p] = kEnd;
           s_live = false;
+          if (MULTI && gl == 0) count_steps(R, s_t);
         } else {
           const uint32_t next = g.adj[s_o + (gm ? __builtin_ctz(gm) : 0)];
           if (gl == 0) row[s_t + 1] = next;
           s_prev = s_cur;
           s_cur = next;
           s_t += 1;
-          if (s_t == length) s_live = false;
+          if (s_t == length) {
+            s_live = false;
+            if (MULTI && gl == 0) count_steps(R, length);
+          }
         }
       }
     }
@@ -565,7 +676,13 @@ k_walk_persistent(
         // Wave-uniform: kept in scalar registers.
         tb.po = uniform64(g.off[prev]);
         tb.pd = uniform64(g.off[prev + 1]) - tb.po;
-        build_table(tb, g.adj, d, lane);
+        // N(prev) much shorter than N(cur): look its keys up in N(cur)
+        // instead of testing every entry of N(cur) against it.
+        if (cfg.sparse_ratio != 0 && d >= kSparseMinDegree && tb.cells >= 2 * kWave &&
+            (uint64_t)cfg.sparse_ratio * tb.pd <= d)
+          tb.kind = 3;
+        else
+          build_table(tb, g.adj, d, lane);
       }
       const uint64_t u = philox_draw(R.seed, R.qid_base + qid, t);
       auto ev = base_eval<ALGO, WEIGHTED, MemberAny>(g, prm, o, prev, t);
@@ -578,12 +695,18 @@ k_walk_persistent(
       ev.mem.po = tb.po;
       ev.mem.pd = tb.pd;
       int64_t idx;
-      if (ALGO == kNode2Vec && tb.kind == 2) {
-        // Pass 1 by merge; the locate re-evaluates one group with searches.
+      if (ALGO == kNode2Vec && (tb.kind == 2 || tb.kind == 3)) {
+        // Pass 1 by merging the sorted rows (kind 2), or from raw weights
+        // and N(prev)'s keys looked up in N(cur) (kind 3).  The locate
+        // evaluates the drawn group's entries one by one: a one-chunk group
+        // of the merge is merged again from its cursor; otherwise against a
+        // hash set of N(prev) (kind 3, when it fits) or by binary searches.
         const QuadSlice qs(o, d);
         const GroupSplit sp(qs.nq);
-        uint64_t gcur;
-        const uint64_t mine = merge_group_totals(ev, qs, sp, tb, lane, gcur);
+        const bool sparse = tb.kind == 3;
+        uint64_t gcur = 0;
+        const uint64_t mine = sparse ? sparse_prev_group_totals(ev, qs, sp, tb, lane)
+                                     : merge_group_totals(ev, qs, sp, tb, lane, gcur);
         const uint64_t incl = wave_incl_scan(mine);
         const uint64_t total = readlane64(incl, kWave - 1);
         idx = -1;
@@ -594,14 +717,19 @@ k_walk_persistent(
           r -= readlane64(incl - mine, gs);
           const uint32_t lo = (uint32_t)gs * sp.gsz;
           const uint32_t len = min(sp.gsz, qs.nq - lo);
-          if (len <= (uint32_t)kWave) {
-            // A one-chunk group (rows up to 16,384 entries): merge it again
-            // from its cursor and pick inside it.
+          if (!sparse && len <= (uint32_t)kWave) {
+            // A one-chunk group (rows up to 16,384 entries).
             uint64_t cur = readlane64(gcur, gs);
             uint64_t w[4], t;
             merge_chunk(ev, qs, tb, lo, lo + len, cur, lane, w, t);
             idx = pick_in_quads(w, qs, lo, len, r, true, 0);
           } else {
+            if (sparse) {
+              build_table(tb, g.adj, d, lane, false);
+              ev.mem.mode = tb.kind == 1 ? 1 : 0;
+              ev.mem.bmask = tb.bmask;
+              ev.mem.shift = tb.shift;
+            }
             idx = (int64_t)wave_locate(ev, qs, lo, len, r);
           }
         }
@@ -613,6 +741,7 @@ k_walk_persistent(
       if (idx < 0) {
         for (uint32_t p = t + 1 + lane; p <= length; p += kWave) row[p] = kEnd;
         if (mine) s_live = false;
+        if (MULTI && lane == src) count_steps(R, t);
       } else {
         const uint32_t next = g.adj[o + (uint64_t)idx];
         if (lane == 0) row[t + 1] = next;
@@ -622,6 +751,7 @@ k_walk_persistent(
           s_t += 1;
           if (s_t == length) s_live = false;
         }
+        if (MULTI && lane == src && t + 1 == length) count_steps(R, length);
       }
       wave_sync_lds();
     }
@@ -679,6 +809,7 @@ hipError_t launch_persistent(const LaunchArgs& a, hipStream_t stream) {
   Reqs<false> rq;
   rq.one.starts = a.starts;
   rq.one.out = a.out;
+  rq.one.steps = nullptr;
   rq.one.n = a.n;
   rq.one.seed = a.seed;
   rq.one.qid_base = a.qid_base;

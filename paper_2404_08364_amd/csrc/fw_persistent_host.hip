@@ -1,6 +1,7 @@
 // Host side of the persistent form: launch configuration (defaults, the
 // tuned per-algorithm configuration, user overrides, validation) and the
 // launch itself, optionally replayed from a captured hipGraph.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -53,7 +54,49 @@ void drop_exec(const GraphKey& key, CachedExec& c) {
   c.head = nullptr;
 }
 
+// Tuned configurations of both forms, per (graph fingerprint, device,
+// algorithm), for the life of the process.
+struct Tuned {
+  TuneCfg persistent, staged;
+  bool have_persistent = false, have_staged = false;
+  bool auto_staged = false;  // FW_MODE_AUTO runs the staged form
+};
+
+std::mutex g_tuned_mu;
+std::map<std::tuple<uint64_t, int, int>, Tuned> g_tuned;
+
+bool find_tuned(const fw_graph* g, int algo, Tuned* out) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  auto it = g_tuned.find(std::make_tuple(g->fingerprint, g->device, algo));
+  if (it == g_tuned.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+uint64_t mix64(uint64_t x) {  // SplitMix64's finaliser
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
 }  // namespace
+
+uint64_t graph_fingerprint(const fw_graph* g, const uint64_t* off, const uint32_t* adj,
+                           const uint32_t* w, const uint8_t* lab) {
+  uint64_t h = mix64(g->nv) ^ mix64(g->ne + 1) * 3 ^ mix64(g->max_deg + 2) * 5 ^
+               mix64(g->max_w + 3) * 7 ^ (w ? 11 : 0) ^ (lab ? 13 : 0);
+  constexpr uint64_t kSamples = 4096;
+  for (uint64_t k = 0; k < kSamples; ++k) {
+    const uint64_t v = g->nv ? k * (g->nv + 1) / kSamples : 0;
+    h = mix64(h ^ off[v]);
+    if (g->ne) {
+      const uint64_t e = k * g->ne / kSamples;
+      h = mix64(h ^ adj[e] ^ ((uint64_t)(w ? w[e] : 0) << 32) ^ ((uint64_t)(lab ? lab[e] : 0) << 24));
+    }
+  }
+  return h;
+}
 
 TuneCfg default_tune(const fw_graph* g, int algo, bool staged) {
   (void)g;
@@ -73,6 +116,7 @@ TuneCfg default_tune(const fw_graph* g, int algo, bool staged) {
     c.hub_min = 17;
     c.wgs_per_cu = 8;  // the kernel is built for 8 wavefronts per SIMD
     c.hash_cells = (algo == 1) ? 1024 : 64;
+    c.sparse_ratio = (algo == 1) ? 64 : 0;
   }
   return c;
 }
@@ -99,13 +143,14 @@ int validate_tune(const fw_graph* g, const TuneCfg& c, bool staged) {
   return FW_OK;
 }
 
-int resolve_tune(const fw_graph* g, int algo, bool staged, const fw_tune* user, TuneCfg* cfg) {
-  TuneCfg c = default_tune(g, algo, staged);
-  if (!staged) {
-    std::lock_guard<std::mutex> lk(g->mu);
-    auto it = g->tuned.find(algo);
-    if (it != g->tuned.end()) c = it->second;
-  }
+int resolve_tune(const fw_graph* g, int algo, int mode, const fw_tune* user, TuneCfg* cfg,
+                 bool* staged) {
+  Tuned t;
+  const bool have = find_tuned(g, algo, &t);
+  const bool st = mode == FW_MODE_STAGED || (mode == FW_MODE_AUTO && have && t.auto_staged);
+  TuneCfg c = default_tune(g, algo, st);
+  if (have && st && t.have_staged) c = t.staged;
+  if (have && !st && t.have_persistent) c = t.persistent;
   if (user) {
     if (user->wg_size) c.wg_size = user->wg_size;
     if (user->slots) c.slots = user->slots;
@@ -113,10 +158,12 @@ int resolve_tune(const fw_graph* g, int algo, bool staged, const fw_tune* user, 
     if (user->hub_min) c.hub_min = user->hub_min;
     if (user->wgs_per_cu) c.wgs_per_cu = user->wgs_per_cu;
     if (user->hash_cells) c.hash_cells = user->hash_cells;
+    if (user->sparse_ratio) c.sparse_ratio = user->sparse_ratio == 0xFFFFFFFFu ? 0 : user->sparse_ratio;
   }
-  const int rc = validate_tune(g, c, staged);
+  const int rc = validate_tune(g, c, st);
   if (rc) return rc;
   *cfg = c;
+  *staged = st;
   return FW_OK;
 }
 
@@ -181,16 +228,17 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
 // Times cfg on the sample: a warm-up launch, then the faster of two timed
 // launches (hipEvents on stream; one launch alone left the choice between
 // close configurations to noise).
-static int time_config(const fw_graph* g, LaunchArgs a, const TuneCfg& cfg, hipStream_t stream,
-                       hipEvent_t e0, hipEvent_t e1, float* ms) {
+static int time_config(const fw_graph* g, LaunchArgs a, const TuneCfg& cfg, bool staged,
+                       hipStream_t stream, hipEvent_t e0, hipEvent_t e1, float* ms) {
   a.cfg = cfg;
   a.cfg.narrow = narrow_products(g->max_w, a.prm);
-  hipError_t e = launch_persistent(a, stream);  // warm-up
+  auto launch = [&]() { return staged ? launch_staged(a, stream) : launch_persistent(a, stream); };
+  hipError_t e = launch();  // warm-up
   *ms = 1e30f;
   for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
     float t = 0;
     e = hipEventRecord(e0, stream);
-    if (e == hipSuccess) e = launch_persistent(a, stream);
+    if (e == hipSuccess) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e1, stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -201,7 +249,8 @@ static int time_config(const fw_graph* g, LaunchArgs a, const TuneCfg& cfg, hipS
 }
 
 int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts, uint64_t n,
-             uint32_t length, uint64_t seed, hipStream_t stream, TuneCfg* best) {
+             uint32_t length, uint64_t seed, hipStream_t stream, TuneCfg* best,
+             bool* best_staged) {
   uint32_t* out = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc((void**)&out, n * ((uint64_t)length + 1) * sizeof(uint32_t));
@@ -223,10 +272,12 @@ int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts,
   a.status = g->d_status;
   a.head = g->d_head + kHeadStride * (g->launches.fetch_add(1) % kHeadSlots);
   a.num_cus = g->num_cus;
-  TuneCfg c = default_tune(g, algo, false), best_c = c;
-  float best_ms = 1e30f;
-  // Coordinate search: occupancy x membership-table size, then the tiny
-  // threshold.  Configurations that do not fit the LDS are skipped.
+  const uint64_t lds_cu = 160 * 1024;  // LDS of a compute unit
+  // Persistent form.  Coordinate search: occupancy x membership-table size,
+  // then the tiny threshold.  Configurations that do not fit the LDS are
+  // skipped.
+  TuneCfg c = default_tune(g, algo, false), best_p = c;
+  float best_p_ms = 1e30f;
   const uint32_t cells[] = {256, 512, 1024, 2048, 4096};
   const uint32_t wgs[] = {3, 4, 5, 6, 7, 8};
   for (uint32_t hc : cells) {
@@ -237,24 +288,66 @@ int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts,
       t.hash_cells = (algo == 1) ? hc : 64;
       t.wgs_per_cu = w;
       if (validate_tune(g, t, false)) continue;
-      if ((uint64_t)t.hash_cells * 16 * w > 160 * 1024) continue;  // would not be resident
+      if ((uint64_t)t.hash_cells * 16 * w > lds_cu) continue;  // would not be resident
       float ms = 0;
-      rc = time_config(g, a, t, stream, e0, e1, &ms);
-      if (!rc && ms < best_ms) {
-        best_ms = ms;
-        best_c = t;
+      rc = time_config(g, a, t, false, stream, e0, e1, &ms);
+      if (!rc && ms < best_p_ms) {
+        best_p_ms = ms;
+        best_p = t;
       }
     }
   }
   for (uint32_t tm : {0u, 8u, 16u}) {
     if (rc) break;
-    TuneCfg t = best_c;
+    TuneCfg t = best_p;
     t.tiny_max = tm;
     float ms = 0;
-    rc = time_config(g, a, t, stream, e0, e1, &ms);
-    if (!rc && ms < best_ms) {
-      best_ms = ms;
-      best_c = t;
+    rc = time_config(g, a, t, false, stream, e0, e1, &ms);
+    if (!rc && ms < best_p_ms) {
+      best_p_ms = ms;
+      best_p = t;
+    }
+  }
+  // node2vec: how much shorter N(prev) must be than N(cur) for the hop to
+  // look N(prev)'s keys up in N(cur) (0: never).
+  for (uint32_t sr : {0u, 16u, 32u, 64u, 128u, 256u}) {
+    if (rc || algo != 1) break;
+    TuneCfg t = best_p;
+    t.sparse_ratio = sr;
+    float ms = 0;
+    rc = time_config(g, a, t, false, stream, e0, e1, &ms);
+    if (!rc && ms < best_p_ms) {
+      best_p_ms = ms;
+      best_p = t;
+    }
+  }
+  // Staged form (section 5.1's block design): workgroup size x hub
+  // threshold d_t x local pool size |P_L| (Appendix C.2's two parameters).
+  TuneCfg best_s = default_tune(g, algo, true);
+  float best_s_ms = 1e30f;
+  const uint32_t wg_sizes[] = {256, 512, 1024};
+  const uint32_t hub_mins[] = {1024, 4096, 16384};
+  const uint32_t pools[] = {32, 64};
+  for (uint32_t wg : wg_sizes) {
+    for (uint32_t hm : hub_mins) {
+      for (uint32_t sl : pools) {
+        if (rc) break;
+        TuneCfg t = default_tune(g, algo, true);
+        t.wg_size = wg;
+        t.hub_min = hm;
+        t.slots = sl;
+        const uint32_t waves = wg / 64;
+        if (t.hash_cells < 64 * waves) t.hash_cells = 64 * waves;
+        const uint64_t lds_wg = 16 * 1024 + (uint64_t)t.hash_cells * 4;
+        t.wgs_per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(32 / waves, lds_cu / lds_wg));
+        if (validate_tune(g, t, true)) continue;
+        float ms = 0;
+        rc = time_config(g, a, t, true, stream, e0, e1, &ms);
+        if (!rc && ms < best_s_ms) {
+          best_s_ms = ms;
+          best_s = t;
+        }
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -268,11 +361,17 @@ int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts,
     if (!rc) rc = set_error(FW_EINVAL, "a start vertex is >= n_vertices");
   }
   if (rc) return rc;
+  Tuned t;
+  t.persistent = best_p;
+  t.staged = best_s;
+  t.have_persistent = t.have_staged = true;
+  t.auto_staged = best_s_ms < best_p_ms;
   {
-    std::lock_guard<std::mutex> lk(g->mu);
-    g->tuned[algo] = best_c;
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[std::make_tuple(g->fingerprint, g->device, algo)] = t;
   }
-  *best = best_c;
+  *best = t.auto_staged ? best_s : best_p;
+  *best_staged = t.auto_staged;
   return FW_OK;
 }
 

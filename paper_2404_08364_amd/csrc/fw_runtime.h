@@ -23,9 +23,9 @@ struct fw_graph {
   int num_cus = 0;
   size_t lds_per_block = 0;                        // device limit, bytes
   uint64_t bytes = 0;
+  uint64_t fingerprint = 0;                        // keys the tuned configurations
   mutable std::atomic<uint64_t> launches{0};       // rotates the head counters
-  mutable std::mutex mu;                           // guards the caches below
-  mutable std::map<int, fw::TuneCfg> tuned;        // per algorithm
+  mutable std::mutex mu;                           // guards the cache below
   mutable void* graph_cache = nullptr;             // captured launch graphs
 };
 
@@ -43,13 +43,19 @@ DevGraph dev_graph(const fw_graph* g);
 int read_status(const fw_graph* g, hipStream_t stream);
 
 // Persistent form: configuration and launch (fw_persistent_host.hip).
-int resolve_tune(const fw_graph* g, int algo, bool staged, const fw_tune* user, TuneCfg* cfg);
+// mode: FW_MODE_PERSISTENT, FW_MODE_STAGED or FW_MODE_AUTO (the tuned form);
+// *staged tells which kernel the configuration is for.
+int resolve_tune(const fw_graph* g, int algo, int mode, const fw_tune* user, TuneCfg* cfg,
+                 bool* staged);
+uint64_t graph_fingerprint(const fw_graph* g, const uint64_t* off, const uint32_t* adj,
+                           const uint32_t* w, const uint8_t* lab);
 hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hipStream_t stream,
                                      bool use_graph, bool staged);
 void release_graph_state(fw_graph* g);
 TuneCfg default_tune(const fw_graph* g, int algo, bool staged);
 int validate_tune(const fw_graph* g, const TuneCfg& c, bool staged);
 int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts, uint64_t n,
-             uint32_t length, uint64_t seed, hipStream_t stream, TuneCfg* best);
+             uint32_t length, uint64_t seed, hipStream_t stream, TuneCfg* best,
+             bool* best_staged);
 
 }  // namespace fw

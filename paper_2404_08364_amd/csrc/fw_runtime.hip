@@ -212,6 +212,7 @@ int fw_graph_upload(const fw_csr* csr, const uint32_t* weights, const uint8_t* l
     delete g;
     return hip_fail(e, "querying the device");
   }
+  g->fingerprint = fw::graph_fingerprint(g, off, adj, weights, labels);
   g->num_cus = prop.multiProcessorCount;
   g->lds_per_block = prop.sharedMemPerBlock;
   auto alloc = [&](void** p, size_t bytes) -> hipError_t {
@@ -310,8 +311,8 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
     e = fw::launch_plain(a, stream);
   } else if (o.mode == FW_MODE_PERSISTENT || o.mode == FW_MODE_AUTO ||
              o.mode == FW_MODE_STAGED) {
-    const bool staged = o.mode == FW_MODE_STAGED;
-    rc = fw::resolve_tune(g, (int)algo, staged, o.tune, &a.cfg);
+    bool staged = false;
+    rc = fw::resolve_tune(g, (int)algo, o.mode, o.tune, &a.cfg, &staged);
     if (rc) return rc;
     a.cfg.narrow = fw::narrow_products(g->max_w, dp);
     e = fw::launch_persistent_checked(g, a, stream, o.use_graph != 0, staged);
@@ -335,7 +336,8 @@ int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32
   if (rc) return rc;
   if (n == 0) return fw::set_error(FW_EINVAL, "empty sample");
   fw::TuneCfg c;
-  rc = fw::autotune(g, (int)algo, dp, starts, n, length, seed, (hipStream_t)stream, &c);
+  bool staged = false;
+  rc = fw::autotune(g, (int)algo, dp, starts, n, length, seed, (hipStream_t)stream, &c, &staged);
   if (rc) return rc;
   if (best) {
     std::memset(best, 0, sizeof(*best));
@@ -345,6 +347,8 @@ int fw_autotune(fw_graph* g, fw_algo algo, const fw_params* params, const uint32
     best->hub_min = c.hub_min;
     best->wgs_per_cu = c.wgs_per_cu;
     best->hash_cells = c.hash_cells;
+    best->mode = staged ? FW_MODE_STAGED : FW_MODE_PERSISTENT;
+    best->sparse_ratio = c.sparse_ratio ? c.sparse_ratio : 0xFFFFFFFFu;
   }
   return FW_OK;
 }

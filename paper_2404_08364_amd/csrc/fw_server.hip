@@ -99,6 +99,11 @@ struct Request {
   ReqState state = kQueued;
   int status = FW_OK;
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+  // A finished request whose region was reclaimed before it was waited for
+  // keeps its rows and hop count here.
+  bool spilled = false;
+  std::vector<uint32_t> spill;
+  uint64_t spill_steps = 0;
 };
 
 constexpr int kMaxAlgos = 4;  // DeepWalk, node2vec, MetaPath, PPR
@@ -143,18 +148,26 @@ namespace {
 
 int fail(int code, const char* msg) { return fw::set_error(code, msg); }
 
+// A request's arena region: its realised-hop counter (in a 256-byte cell),
+// its start vertices (rounded up to 256 bytes), then its rows.
+constexpr uint64_t kCounterBytes = 256;
+
+uint64_t starts_bytes(uint64_t n) { return (n * 4 + 255) & ~255ull; }
+
 uint64_t request_bytes(uint64_t n, uint32_t length) {
-  const uint64_t starts = (n * 4 + 255) & ~255ull;
-  return starts + n * ((uint64_t)length + 1) * 4;
+  return kCounterBytes + starts_bytes(n) + n * ((uint64_t)length + 1) * 4;
 }
 
 // Launches one batch (scheduler thread, lock not held).
 hipError_t launch_batch(fw_server* s, Batch& b) {
   hipError_t e = hipSuccess;
   for (auto& r : b.reqs) {
+    // The counter starts at zero and goes over with the start vertices.
     uint8_t* h = s->h_arena + r->off;
-    std::memcpy(h, r->starts.data(), r->n * 4);
-    e = hipMemcpyAsync(s->d_arena + r->off, h, r->n * 4, hipMemcpyHostToDevice, b.stream);
+    std::memset(h, 0, kCounterBytes);
+    std::memcpy(h + kCounterBytes, r->starts.data(), r->n * 4);
+    e = hipMemcpyAsync(s->d_arena + r->off, h, kCounterBytes + r->n * 4, hipMemcpyHostToDevice,
+                       b.stream);
     if (e != hipSuccess) return e;
   }
   const fw::DevGraph dg = fw::dev_graph(s->g);
@@ -164,8 +177,10 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
     for (auto& r : b.reqs) {
       if (r->algo != a) continue;
       fw::ReqDesc& d = b.h_desc[a][k];
-      d.starts = reinterpret_cast<const uint32_t*>(s->d_arena + r->off);
-      d.out = reinterpret_cast<uint32_t*>(s->d_arena + r->off + ((r->n * 4 + 255) & ~255ull));
+      d.steps = reinterpret_cast<unsigned long long*>(s->d_arena + r->off);
+      d.starts = reinterpret_cast<const uint32_t*>(s->d_arena + r->off + kCounterBytes);
+      d.out = reinterpret_cast<uint32_t*>(s->d_arena + r->off + kCounterBytes +
+                                          starts_bytes(r->n));
       d.n = r->n;
       d.seed = r->seed;
       d.qid_base = 0;
@@ -193,12 +208,40 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
     if (e != hipSuccess) return e;
   }
   for (auto& r : b.reqs) {
-    const uint64_t so = (r->n * 4 + 255) & ~255ull;
+    const uint64_t so = kCounterBytes + starts_bytes(r->n);
     e = hipMemcpyAsync(s->h_arena + r->off + so, s->d_arena + r->off + so,
                        r->n * ((uint64_t)r->length + 1) * 4, hipMemcpyDeviceToHost, b.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->h_arena + r->off, s->d_arena + r->off, sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, b.stream);
     if (e != hipSuccess) return e;
   }
   return hipEventRecord(b.done, b.stream);
+}
+
+// Admission is in arrival order, and a finished request holds its region
+// until it is waited for.  When the next request does not fit, finished
+// requests nobody has collected yet move their rows to host memory and give
+// their regions back, so that the order of the client's waits cannot stall
+// admission.  Returns whether any region was freed.  (Lock held.)
+bool spill_finished(fw_server* s) {
+  bool freed = false;
+  for (auto& kv : s->reqs) {
+    auto& r = kv.second;
+    if (!r->has_region || (r->state != kDone && r->state != kFailed)) continue;
+    if (r->state == kDone) {
+      const uint64_t so = kCounterBytes + starts_bytes(r->n);
+      const uint64_t cells = r->n * ((uint64_t)r->length + 1);
+      r->spill.resize(cells);
+      std::memcpy(r->spill.data(), s->h_arena + r->off + so, cells * 4);
+      std::memcpy(&r->spill_steps, s->h_arena + r->off, sizeof(uint64_t));
+      r->spilled = true;
+    }
+    s->arena->release(r->off);
+    r->has_region = false;
+    freed = true;
+  }
+  return freed;
 }
 
 void scheduler(fw_server* s) {
@@ -236,7 +279,10 @@ void scheduler(fw_server* s) {
           s->queue.pop_front();
           continue;
         }
-        if (!s->arena->alloc(r->bytes, &r->off)) break;
+        if (!s->arena->alloc(r->bytes, &r->off)) {
+          if (spill_finished(s)) continue;
+          break;
+        }
         r->has_region = true;
         r->state = kRunning;
         r->t_admit = now_ns();
@@ -301,7 +347,8 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   if (s->opts.max_inflight > 16 || s->opts.max_batch_requests > 4096)
     return fail(FW_EINVAL, "max_inflight <= 16 and max_batch_requests <= 4096");
   for (int a = 0; a < kMaxAlgos; ++a) {
-    const int rc = fw::resolve_tune(g, a, false, nullptr, &s->cfg[a]);
+    bool staged = false;
+    const int rc = fw::resolve_tune(g, a, FW_MODE_PERSISTENT, nullptr, &s->cfg[a], &staged);
     if (rc) return rc;
   }
   hipError_t e = hipSetDevice(g->device);
@@ -391,11 +438,19 @@ int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_sta
     stats->n = r->n;
     stats->length = r->length;
     stats->status = r->status;
+    stats->steps = 0;
+    if (r->status == FW_OK && r->spilled)
+      stats->steps = r->spill_steps;
+    else if (r->status == FW_OK && r->has_region)
+      std::memcpy(&stats->steps, s->h_arena + r->off, sizeof(uint64_t));
   }
   int rc = r->status;
   if (rc == FW_OK && out_host) {
-    const uint64_t so = (r->n * 4 + 255) & ~255ull;
-    std::memcpy(out_host, s->h_arena + r->off + so, r->n * ((uint64_t)r->length + 1) * 4);
+    const uint64_t cells = r->n * ((uint64_t)r->length + 1);
+    if (r->spilled)
+      std::memcpy(out_host, r->spill.data(), cells * 4);
+    else
+      std::memcpy(out_host, s->h_arena + r->off + kCounterBytes + starts_bytes(r->n), cells * 4);
   }
   release_request(s, r);
   if (rc != FW_OK) return fail(rc, rc == FW_ECANCELED ? "request cancelled" : "request failed");

@@ -50,7 +50,8 @@ class Tune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_uint32), ("slots", ctypes.c_uint32),
                 ("tiny_max", ctypes.c_uint32), ("hub_min", ctypes.c_uint32),
                 ("wgs_per_cu", ctypes.c_uint32), ("fetch", ctypes.c_uint32),
-                ("hash_cells", ctypes.c_uint32)]
+                ("hash_cells", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("sparse_ratio", ctypes.c_uint32)]
 
 
 class WalkOpts(ctypes.Structure):
@@ -76,7 +77,7 @@ class ServerOpts(ctypes.Structure):
 class ReqStats(ctypes.Structure):
     _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
                 ("done_ns", ctypes.c_uint64), ("n", ctypes.c_uint64), ("length", ctypes.c_uint32),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("steps", ctypes.c_uint64)]
 
 
 def _bind(lib):
@@ -265,8 +266,9 @@ def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
 
 def autotune(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
              stream=None) -> dict:
-    """Tunes the persistent form on the queries of `starts` (a device tensor
-    holding a sample of the workload) and returns the chosen configuration."""
+    """Tunes the persistent and the staged form on the queries of `starts` (a
+    device tensor holding a sample of the workload) and returns the faster
+    configuration ("mode" names its form: 2 persistent, 3 staged)."""
     import torch
     starts = starts.contiguous()
     if stream is None:
@@ -366,12 +368,14 @@ class Server:
             raise FWError(rc, "fw_server_poll")
         return rc == 1
 
-    def wait(self, ticket: int):
+    def wait(self, ticket: int, rows: bool = True):
+        """Returns (rows as uint32 [n, length + 1], stats); rows=False skips
+        the copy of the rows and returns None for them."""
         shape = self._shapes.pop(ticket)
-        out = np.empty(shape, dtype=np.uint32)
+        out = np.empty(shape, dtype=np.uint32) if rows else None
         st = ReqStats()
-        _check(_lib.fw_server_wait(self._h, ticket, out.ctypes.data, ctypes.byref(st)),
-               "fw_server_wait")
+        _check(_lib.fw_server_wait(self._h, ticket, out.ctypes.data if rows else None,
+                                   ctypes.byref(st)), "fw_server_wait")
         return out, {k: getattr(st, k) for k, _ in ReqStats._fields_}
 
     def close(self):

@@ -408,6 +408,33 @@ def test_merge_membership_windows(env, cells, d):
            tune=fw.make_tune(hash_cells=cells, tiny_max=1))
 
 
+def _hub_with_parallel_edges(weighted):
+    """Hub 0 with 3,000 leaves, parallel edges to 5 (three) and 7 (two), and a
+    self-loop; vertex 5 has parallel edges to 8, a self-loop, and edges to 6
+    and 7; vertex 10 has 100 neighbours.  Node2vec hops from the hub after 5
+    or 10 take the sparse-N(prev) pass."""
+    rng = np.random.default_rng(77)
+    edges = [(0, i, int(rng.integers(1, 60_000)), 0) for i in range(1, 3001)]
+    edges += [(0, 5, 7, 0), (0, 5, 9, 0), (0, 7, 11, 0), (0, 0, 5, 0)]
+    edges += [(5, 8, 3, 0), (5, 8, 4, 0), (5, 5, 2, 0), (5, 6, 1, 0), (5, 7, 13, 0)]
+    edges += [(10, j, int(rng.integers(1, 100)), 0) for j in range(11, 111)]
+    return csr_from_edges(3001, edges, weights=weighted, labels=False)
+
+
+@pytest.mark.parametrize("weighted", [True, False])
+@pytest.mark.parametrize("ratio", [1, 16, 0xFFFFFFFF])
+def test_node2vec_sparse_prev_edge_cases(env, weighted, ratio):
+    """Parallel edges in both rows, self-loops, prev repeated in N(cur):
+    the same walks whether N(prev)'s keys are looked up in N(cur) or every
+    entry of N(cur) is tested against N(prev)."""
+    torch, fw = env
+    g = _hub_with_parallel_edges(weighted)
+    starts = np.array([5] * 96 + [10] * 96 + [0] * 32 + list(range(11, 43)), dtype=np.uint32)
+    for f in [(1, 2, 4), (4, 2, 1), (3, 0, 5), (0, 7, 2)]:
+        _check(env, g, "node2vec", f, (), starts, 6, 1357, "persistent",
+               tune=fw.make_tune(sparse_ratio=ratio, tiny_max=1))
+
+
 def test_graph_replay_matches_eager(env, powerlaw):
     """The captured hipGraph of the persistent launch replays to the same
     walks every time, with eager work and synchronisation in between."""
@@ -518,8 +545,16 @@ def test_autotune_then_walks_match(env, powerlaw):
     st = torch.from_numpy(starts.astype(np.int32)).cuda()
     best = fw.autotune(G, "node2vec", prm, st[::4].contiguous(), 10, 1)
     assert best["wgs_per_cu"] >= 1 and best["hash_cells"] >= 64 and best["tiny_max"] <= 16
-    for mode in ("auto", "persistent"):
+    assert best["mode"] in (2, 3)
+    exp = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts, 10, 4)
+    for mode in ("auto", "persistent", "staged"):
         got = fw.walk(G, "node2vec", prm, st, 10, 4, mode=mode)
         torch.cuda.synchronize()
-        exp = oracle.walk(g, "node2vec", oracle.params(1, 2, 4), starts, 10, 4)
         assert_rows_equal(got.cpu().numpy().view(np.uint32), exp, f"after autotune {mode}")
+    # A second upload of the same graph has the same fingerprint and finds
+    # the tuned configurations.
+    G2 = fw.Graph.of(g)
+    got = fw.walk(G2, "node2vec", prm, st, 10, 4, mode="auto")
+    torch.cuda.synchronize()
+    assert_rows_equal(got.cpu().numpy().view(np.uint32), exp, "re-uploaded graph, auto")
+    G2.free()

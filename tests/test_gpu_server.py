@@ -73,6 +73,7 @@ def test_mix_equals_alone_and_oracle(env):
         exp = oracle.walk(g, algo, _oracle_params(algo, f, sch), st, L, seed)
         assert_rows_equal(paths, exp, f"served {algo} n={len(st)} L={L}")
         assert stats["status"] == 0 and stats["done_ns"] >= stats["admit_ns"] >= stats["submit_ns"]
+        assert stats["steps"] == int((paths[:, 1:] != 0xFFFFFFFF).sum())
         alone = gpu_walk(torch, fw, G, algo, _fw_params(fw, algo, f, sch), st, L, seed, "persistent")
         assert_rows_equal(paths, alone, "served vs alone")
 
@@ -97,6 +98,25 @@ def test_admission_by_memory(env):
         with pytest.raises(fw.FWError) as e:
             srv.submit("deepwalk", None, np.array([g.n_vertices], np.uint32), 5, 1)
         assert e.value.status == fw.EINVAL
+    finally:
+        srv.close()
+
+
+def test_waits_in_reverse_order_under_a_tight_budget(env):
+    """The budget holds two requests at a time; the client waits for the
+    last request first.  Finished requests that are not collected yet give
+    their memory back, so every request is admitted and served."""
+    torch, fw, g, G = env
+    reqs = _requests(g, 8, 3)
+    need = max(256 + len(st) * 4 + 256 + len(st) * (L + 1) * 4 for (_, _, _, st, L, _) in reqs)
+    srv = fw.Server(G, mem_budget_bytes=2 * need, max_inflight=2, max_batch_requests=1)
+    try:
+        tickets = [srv.submit(a, _fw_params(fw, a, f, s), st, L, sd) for (a, f, s, st, L, sd) in reqs]
+        for (a, f, s, st, L, sd), t in reversed(list(zip(reqs, tickets))):
+            paths, stats = srv.wait(t)
+            assert_rows_equal(paths, oracle.walk(g, a, _oracle_params(a, f, s), st, L, sd),
+                              "reverse-order wait")
+            assert stats["steps"] == int((paths[:, 1:] != 0xFFFFFFFF).sum())
     finally:
         srv.close()
 
