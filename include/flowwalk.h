@@ -212,6 +212,26 @@ int fw_walk_ex(const fw_graph* g, fw_algo algo, const fw_params* params,
                const uint32_t* starts, uint64_t n, uint32_t length, uint64_t seed,
                uint32_t* out_paths, const fw_walk_opts* opts);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the walk of
+ * fw_walk in FW_MODE_PERSISTENT with the graph's tuned configuration,
+ * enqueued on `stream` (a hipStream_t, NULL = null stream) without waiting
+ * and without allocating anything.  The task-pool head counter its
+ * wavefronts claim queries from lives in a 256-byte static device array of
+ * the library, one per GPU, held until the process ends (the other entry
+ * points use counters allocated with the graph).  That counter is shared by
+ * every fw_walk_noalloc call on the GPU: calls whose launches overlap on the
+ * device (on different streams, or from several threads) race and may skip
+ * or repeat queries; calls on one stream run one after the other and are
+ * safe.  Each launch resets the counter with a one-thread kernel (no memset).
+ * Arguments and rows as fw_walk's (query i has id i).  The graph must live
+ * on the current device.  Host-side argument errors are returned; a start
+ * vertex >= V found by the kernel is reported by fw_sync on the same stream.
+ * Errors: as fw_walk, FW_EINVAL for a graph of another device, FW_EHIP. */
+int fw_walk_noalloc(const fw_graph* g, fw_algo algo, const fw_params* params,
+                    const uint32_t* starts, uint64_t n, uint32_t length, uint64_t seed,
+                    uint32_t* out_paths, void* stream);
+
 /* Autotuner (the hyper-parameter study of Appendix C.2, run on the target
  * GPU): times candidate configurations on the n queries of `starts`
  * (device, a sample of the real query set):

@@ -15,7 +15,7 @@ CSRC = PKG / "csrc"
 LIB = PKG / "libflowwalk.so"
 SOURCES = ["fw_runtime.hip", "fw_plain.hip", "fw_persistent.hip", "fw_staged.hip",
            "fw_persistent_host.hip", "fw_server.hip", "fw_reservoir.hip", "fw_batch.hip",
-           "fw_tasks.hip"]
+           "fw_tasks.hip", "fw_noalloc.hip"]
 ARCH = os.environ.get("FW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

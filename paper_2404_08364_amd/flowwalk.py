@@ -90,6 +90,7 @@ def _bind(lib):
         "fw_walk": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp], i32),
         "fw_walk_ex": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp,
                         ctypes.POINTER(WalkOpts)], i32),
+        "fw_walk_noalloc": ([vp, i32, ctypes.POINTER(Params), vp, u64, u32, u64, vp, vp], i32),
         "fw_sync": ([vp, vp], i32),
         "fw_count_steps": ([vp, u64, u32, vp, ctypes.POINTER(u64)], i32),
         "fw_sample_tasks": ([i32, vp, u64, u32, u64, vp, vp], i32),
@@ -261,6 +262,30 @@ def walk(graph: Graph, algo, prm: Params | None, starts, length: int, seed: int,
     rc = walk_ptr(graph, algo, prm, starts.data_ptr(), n, length, seed, out.data_ptr(), mode,
                   stream, async_, qid_base, tune, use_graph, sampler)
     _check(rc, "fw_walk_ex")
+    return out
+
+
+def walk_noalloc(graph: Graph, algo, prm: Params | None, starts, out, length: int, seed: int,
+                 stream=None):
+    """fw_walk_noalloc: enqueues the persistent walk into the caller's `out`
+    (contiguous int32 [n, length + 1]) on `stream` without allocating and
+    without waiting; fw_sync (sync()) reports a bad start vertex."""
+    import torch
+    if starts.device.type != "cuda" or out.device.type != "cuda":
+        raise ValueError("starts and out must be device tensors")
+    if starts.dtype not in (torch.int32, torch.uint32) or not starts.is_contiguous():
+        raise ValueError("starts must be a contiguous int32 tensor")
+    n = starts.shape[0]
+    if out.dtype not in (torch.int32, torch.uint32) or not out.is_contiguous() \
+            or out.numel() != n * (length + 1):
+        raise ValueError("out must be a contiguous int32 tensor of n * (length + 1) entries")
+    if stream is None:
+        stream = torch.cuda.current_stream(starts.device)
+    a = ALGOS.get(algo, algo)
+    rc = _lib.fw_walk_noalloc(graph.handle, a, None if prm is None else ctypes.byref(prm),
+                              starts.data_ptr(), n, length, seed, out.data_ptr(),
+                              _stream_handle(stream))
+    _check(rc, "fw_walk_noalloc")
     return out
 
 
