@@ -441,8 +441,9 @@ def main():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--autotune-sample", type=int, default=0,
                     help="queries the autotuner times (0 = every k-th query, at least "
-                         "65536 and 1/64 of the workload, so that the sample's few long "
-                         "walks do not decide the timings)")
+                         "262144 and 1/16 of the workload: a sample must hold many times "
+                         "the 32,768 queries the resident wavefronts keep in flight, or "
+                         "the tail of its last walks decides the timings)")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="seconds of arrivals per offered rate (0 = no serve phase)")
     ap.add_argument("--serve-rates", default="250,500,1000,2000",
@@ -545,7 +546,7 @@ def main():
 
     tuned = None
     if args.autotune and args.mode in ("persistent", "auto"):
-        want = args.autotune_sample or max(65536, n // 64)
+        want = args.autotune_sample or max(262144, n // 16)
         sample = starts[:: max(1, n // want)].contiguous()
         t_at = time.time()
         tuned = fw.autotune(G, algo, prm, sample, L, seed, stream=stream)

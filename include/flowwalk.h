@@ -175,7 +175,7 @@ typedef struct fw_tune {
                             d(prev) computes its total from the raw weights
                             and looks N(prev)'s ids up in N(cur), instead of
                             testing every entry of N(cur) against N(prev)
-                            (0 = tuned/default 64, 0xFFFFFFFF = never) */
+                            (0 = tuned/default 128, 0xFFFFFFFF = never) */
 } fw_tune;
 
 /* How each hop picks its neighbour (fw_walk_opts.sampler).

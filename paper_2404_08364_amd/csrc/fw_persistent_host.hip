@@ -116,7 +116,7 @@ TuneCfg default_tune(const fw_graph* g, int algo, bool staged) {
     c.hub_min = 17;
     c.wgs_per_cu = 8;  // the kernel is built for 8 wavefronts per SIMD
     c.hash_cells = (algo == 1) ? 1024 : 64;
-    c.sparse_ratio = (algo == 1) ? 64 : 0;
+    c.sparse_ratio = (algo == 1) ? 128 : 0;
   }
   return c;
 }
