@@ -342,6 +342,60 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
                 ceiling=ceiling, sweep=out)
 
 
+def large_record(fw, synth, torch, log, workload="chunglu227m_n2v"):
+    """One timed persistent pass of the largest workload (227M vertices,
+    ~2.7G stored edges, node2vec from all 10,000,000 starts) with the default
+    configuration, generated without the disk cache; the graph is freed
+    afterwards.  Counter traffic comes from profiles/ when the kernel
+    sources match."""
+    t0 = time.time()
+    g = synth.load_recipe_graph(workload, use_cache=False)
+    log(f"graph {workload}: V={g.n_vertices} E={g.n_edges} ({time.time() - t0:.1f} s)")
+    G = fw.Graph.of(g)
+    algo, prm, walk = recipe_params(fw, synth.RECIPES[workload])
+    L, seed = walk["length"], walk["seed"]
+    starts_np = synth.recipe_starts(workload, g)
+    n = starts_np.shape[0]
+    st = torch.from_numpy(starts_np.view(np.int32)).cuda()
+    out = torch.empty((n, L + 1), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    fw.walk(G, algo, prm, st, L, seed, out=out, mode="persistent", stream=stream, async_=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_wall) * 1e3
+    fw.sync(G, stream)
+    ms = e0.elapsed_time(e1)
+    deg = torch.from_numpy(np.diff(np.asarray(g.offsets)).astype(np.int64)).cuda()
+    acc = account(torch, out, deg, byte_model(algo, g.weights is not None, g.labels is not None))
+    del deg, out, st
+    G.free()
+    del g
+    torch.cuda.empty_cache()
+    achieved = acc["bytes"] / (ms / 1e3) / 1e9
+    traffic, traffic_source = None, None
+    tfile = ROOT / "profiles" / f"traffic_{workload}_persistent.json"
+    if tfile.exists():
+        t = json.loads(tfile.read_text())
+        if t.get("kernel_source") == kernel_source_hash():
+            traffic = t.get("hbm_bytes_per_launch")
+            traffic_source = (f"profiles/{tfile.name}: counters of an earlier profiled run of "
+                              f"the same kernel sources ({t['kernel_source']})")
+    r = dict(workload=workload, description=WORKLOADS[workload], mode="persistent",
+             queries=n, length=L, ms_per_pass=ms, wall_ms=wall_ms,
+             value=acc["hops"] / (ms / 1e3), unit="walk steps/s", hops=acc["hops"],
+             neighbours_scanned=acc["scanned"], algorithmic_bytes_per_launch=acc["bytes"],
+             hbm_gbps_algorithmic=achieved,
+             roofline=roofline_record(achieved, traffic, traffic_source),
+             traffic_gbps=traffic / (ms / 1e3) / 1e9 if traffic else None)
+    log(f"{workload}: {ms:.1f} ms per pass, {r['value'] / 1e6:.2f} M steps/s, "
+        f"{achieved:.0f} GB/s algorithmic")
+    return r
+
+
 def sampler_sweep():
     """One hop from the hub of a star graph (d leaves, weights U[1,255]) for
     every query, in the plain walker (one wavefront per query), with each
@@ -430,7 +484,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22_n2v", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="persistent", choices=["plain", "persistent", "auto"])
+    ap.add_argument("--mode", default="persistent", choices=["plain", "persistent", "auto", "staged"])
     ap.add_argument("--compare-plain", type=int, default=1)
     ap.add_argument("--plain-slices", type=int, default=1,
                     help="run the plain comparison as this many launches over consecutive "
@@ -460,6 +514,9 @@ def main():
                          "request is the serve workload's own walk")
     ap.add_argument("--queries", type=int, default=0,
                     help="time only the first N queries of the workload (0 = all)")
+    ap.add_argument("--large", type=int, default=1,
+                    help="also time one persistent pass of the 227M-vertex Chung-Lu node2vec "
+                         "workload from all 10M starts (the 'large' record; 0 = skip)")
     ap.add_argument("--host-batches", type=int, default=0,
                     help="also time fw_walk_host (rows to host memory) in this many batches")
     ap.add_argument("--task-sweep", action="store_true",
@@ -545,7 +602,7 @@ def main():
         return wall * 1e3 / steps, float(np.mean(kern_ms)), kern_ms
 
     tuned = None
-    if args.autotune and args.mode in ("persistent", "auto"):
+    if args.autotune and args.mode in ("persistent", "auto", "staged"):
         want = args.autotune_sample or max(262144, n // 16)
         sample = starts[:: max(1, n // want)].contiguous()
         t_at = time.time()
@@ -646,6 +703,12 @@ def main():
                               args.serve_max_requests, 4 << 30, log, args.serve_mix, same,
                               args.serve_inflight, args.serve_ceiling)
 
+    large = None
+    if args.large and args.workload != "chunglu227m_n2v":
+        G.free()
+        torch.cuda.empty_cache()
+        large = large_record(fw, synth, torch, log)
+
     res = {
         "metric": METRIC,
         "value": value,
@@ -681,6 +744,7 @@ def main():
         "host_batches": host,
         "cpu_baseline": cpu,
         "latency": latency,
+        "large": large,
         "tuned": tuned,
         "kernel_source": kernel_source_hash(),
     }
