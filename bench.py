@@ -215,7 +215,8 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
 
 def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
                 budget: int, log, mix: str = "mixed", graph=None, inflight: int = 4,
-                ceiling_requests: int = 4000, check_every: int = 64):
+                ceiling_requests: int = 4000, check_every: int = 64, batch: int = 512,
+                small: int = 0):
     """Poisson request streams against the served form, one per offered rate
     (each for `seconds` of arrivals, capped at `max_requests` requests);
     returns latency and throughput per rate, and the served form's ceiling
@@ -261,7 +262,7 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
         starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77 + k)
         offs = np.concatenate([[0], np.cumsum(sizes)])
         srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=inflight,
-                        max_batch_requests=512)
+                        max_batch_requests=batch, small_max_queries=small)
         tickets = [None] * n_req
         sched_ns = [0] * n_req
         lat = np.zeros(n_req)
@@ -335,7 +336,8 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
     kept = [r for r in out if r["keeps_up"]]
     head = max(kept, key=lambda r: r["offered_rate_per_s"]) if kept else out[0]
     return dict(workload=workload, mem_budget_bytes=budget,
-                request_mix=mix_text,
+                max_inflight=inflight, max_batch_requests=batch,
+                small_max_queries=small or 2048, request_mix=mix_text,
                 p50_ms=head["p50_ms"], p99_ms=head["p99_ms"],
                 at_rate_per_s=head["offered_rate_per_s"],
                 note="p50/p99 at the highest offered rate the server kept up with",
@@ -507,6 +509,11 @@ def main():
                     help="requests submitted at once to measure the served form's ceiling "
                          "on the same mix (0 = skip)")
     ap.add_argument("--serve-workload", default="rmat24_serve")
+    ap.add_argument("--serve-batch", type=int, default=512,
+                    help="requests per batch of the server (max_batch_requests, <= 4096)")
+    ap.add_argument("--serve-small", type=int, default=0,
+                    help="requests of at most this many queries complete in their batch's "
+                         "first phase (0 = the server's default, 2048)")
     ap.add_argument("--serve-inflight", type=int, default=4,
                     help="batches the server keeps on the GPU at once (1..16)")
     ap.add_argument("--serve-mix", default="mixed", choices=["mixed", "recipe"],
@@ -701,7 +708,8 @@ def main():
         same = (g, G) if args.serve_workload == args.workload else None
         latency = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
                               args.serve_max_requests, 4 << 30, log, args.serve_mix, same,
-                              args.serve_inflight, args.serve_ceiling)
+                              args.serve_inflight, args.serve_ceiling, batch=args.serve_batch,
+                              small=args.serve_small)
 
     large = None
     if args.large and args.workload != "chunglu227m_n2v":

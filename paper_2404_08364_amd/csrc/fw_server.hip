@@ -99,6 +99,7 @@ struct Request {
   ReqState state = kQueued;
   int status = FW_OK;
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+  bool small = false;  // runs in its batch's first phase
   // A finished request whose region was reclaimed before it was waited for
   // keeps its rows and hop count here.
   bool spilled = false;
@@ -108,15 +109,24 @@ struct Request {
 
 constexpr int kMaxAlgos = 4;  // DeepWalk, node2vec, MetaPath, PPR
 
+// A batch runs in two phases on its stream: first one launch per algorithm
+// over its small requests (n <= small_max_queries) and their copies back,
+// then the same for the large ones.  Each phase ends with an event, so small
+// requests complete without waiting for the large ones of their batch.
+constexpr int kPhases = 2;
+
 struct Batch {
   std::vector<std::shared_ptr<Request>> reqs;
-  hipEvent_t done = nullptr;
+  hipEvent_t done = nullptr;        // end of the last phase
+  hipEvent_t small_done = nullptr;  // end of the small-request phase
+  bool small_pending = false;       // small_done recorded, not yet observed
   bool busy = false;
-  // Per algorithm: descriptor table + prefix (device and pinned staging).
-  fw::ReqDesc* d_desc[kMaxAlgos] = {};
-  uint64_t* d_prefix[kMaxAlgos] = {};
-  fw::ReqDesc* h_desc[kMaxAlgos] = {};
-  uint64_t* h_prefix[kMaxAlgos] = {};
+  // Per (phase, algorithm): descriptor table + prefix (device and pinned
+  // staging).
+  fw::ReqDesc* d_desc[kPhases * kMaxAlgos] = {};
+  uint64_t* d_prefix[kPhases * kMaxAlgos] = {};
+  fw::ReqDesc* h_desc[kPhases * kMaxAlgos] = {};
+  uint64_t* h_prefix[kPhases * kMaxAlgos] = {};
   uint64_t* d_head = nullptr;  // kMaxAlgos counters, 128 B apart
   hipStream_t stream = nullptr;
 };
@@ -171,52 +181,82 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
     if (e != hipSuccess) return e;
   }
   const fw::DevGraph dg = fw::dev_graph(s->g);
-  for (int a = 0; a < kMaxAlgos; ++a) {
-    uint32_t k = 0;
-    uint64_t total = 0;
-    for (auto& r : b.reqs) {
-      if (r->algo != a) continue;
-      fw::ReqDesc& d = b.h_desc[a][k];
-      d.steps = reinterpret_cast<unsigned long long*>(s->d_arena + r->off);
-      d.starts = reinterpret_cast<const uint32_t*>(s->d_arena + r->off + kCounterBytes);
-      d.out = reinterpret_cast<uint32_t*>(s->d_arena + r->off + kCounterBytes +
-                                          starts_bytes(r->n));
-      d.n = r->n;
-      d.seed = r->seed;
-      d.qid_base = 0;
-      d.length = r->length;
-      d.pad = 0;
-      d.prm = r->prm;
-      b.h_prefix[a][k] = total;
-      total += r->n;
-      ++k;
-    }
-    if (!k) continue;
-    b.h_prefix[a][k] = total;
-    e = hipMemcpyAsync(b.d_desc[a], b.h_desc[a], k * sizeof(fw::ReqDesc), hipMemcpyHostToDevice,
-                       b.stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(b.d_prefix[a], b.h_prefix[a], (k + 1) * sizeof(uint64_t),
+  b.small_pending = false;
+  for (int ph = 0; ph < kPhases; ++ph) {
+    const bool small = ph == 0;
+    bool any = false;
+    for (int a = 0; a < kMaxAlgos; ++a) {
+      const int ta = ph * kMaxAlgos + a;
+      uint32_t k = 0;
+      uint64_t total = 0;
+      for (auto& r : b.reqs) {
+        if (r->algo != a || r->small != small) continue;
+        fw::ReqDesc& d = b.h_desc[ta][k];
+        d.steps = reinterpret_cast<unsigned long long*>(s->d_arena + r->off);
+        d.starts = reinterpret_cast<const uint32_t*>(s->d_arena + r->off + kCounterBytes);
+        d.out = reinterpret_cast<uint32_t*>(s->d_arena + r->off + kCounterBytes +
+                                            starts_bytes(r->n));
+        d.n = r->n;
+        d.seed = r->seed;
+        d.qid_base = 0;
+        d.length = r->length;
+        d.pad = 0;
+        d.prm = r->prm;
+        b.h_prefix[ta][k] = total;
+        total += r->n;
+        ++k;
+      }
+      if (!k) continue;
+      any = true;
+      b.h_prefix[ta][k] = total;
+      e = hipMemcpyAsync(b.d_desc[ta], b.h_desc[ta], k * sizeof(fw::ReqDesc),
                          hipMemcpyHostToDevice, b.stream);
-    if (e != hipSuccess) return e;
-    fw::ReqTable t{b.d_desc[a], b.d_prefix[a], k, total};
-    fw::TuneCfg cfg = s->cfg[a];
-    cfg.narrow = 1;
-    for (uint32_t i = 0; i < k; ++i) cfg.narrow &= fw::narrow_products(s->g->max_w, b.h_desc[a][i].prm);
-    e = fw::launch_persistent_multi(a, dg, t, s->d_status, b.d_head + 16 * a, s->g->num_cus, cfg,
-                                    b.stream);
-    if (e != hipSuccess) return e;
-  }
-  for (auto& r : b.reqs) {
-    const uint64_t so = kCounterBytes + starts_bytes(r->n);
-    e = hipMemcpyAsync(s->h_arena + r->off + so, s->d_arena + r->off + so,
-                       r->n * ((uint64_t)r->length + 1) * 4, hipMemcpyDeviceToHost, b.stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->h_arena + r->off, s->d_arena + r->off, sizeof(uint64_t),
-                         hipMemcpyDeviceToHost, b.stream);
-    if (e != hipSuccess) return e;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b.d_prefix[ta], b.h_prefix[ta], (k + 1) * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, b.stream);
+      if (e != hipSuccess) return e;
+      fw::ReqTable t{b.d_desc[ta], b.d_prefix[ta], k, total};
+      fw::TuneCfg cfg = s->cfg[a];
+      cfg.narrow = 1;
+      for (uint32_t i = 0; i < k; ++i)
+        cfg.narrow &= fw::narrow_products(s->g->max_w, b.h_desc[ta][i].prm);
+      // The phases of one algorithm run one after the other on this stream
+      // and share its head counter.
+      e = fw::launch_persistent_multi(a, dg, t, s->d_status, b.d_head + 16 * a, s->g->num_cus,
+                                      cfg, b.stream);
+      if (e != hipSuccess) return e;
+    }
+    if (!any) continue;
+    for (auto& r : b.reqs) {
+      if (r->small != small) continue;
+      const uint64_t so = kCounterBytes + starts_bytes(r->n);
+      e = hipMemcpyAsync(s->h_arena + r->off + so, s->d_arena + r->off + so,
+                         r->n * ((uint64_t)r->length + 1) * 4, hipMemcpyDeviceToHost, b.stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->h_arena + r->off, s->d_arena + r->off, sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, b.stream);
+      if (e != hipSuccess) return e;
+    }
+    if (small) {
+      e = hipEventRecord(b.small_done, b.stream);
+      if (e != hipSuccess) return e;
+      b.small_pending = true;
+    }
   }
   return hipEventRecord(b.done, b.stream);
+}
+
+// Marks the still-running requests of a batch (all of them, or the small
+// ones) finished, by the status of the event that covered them.  (Lock held.)
+void finish(fw_server* s, Batch& b, hipError_t q, bool small_only) {
+  const uint64_t t = now_ns();
+  for (auto& r : b.reqs) {
+    if (r->state != kRunning || (small_only && !r->small)) continue;
+    r->state = (q == hipSuccess) ? kDone : kFailed;
+    if (q != hipSuccess) r->status = FW_EHIP;
+    r->t_done = t;
+  }
+  s->cv_done.notify_all();
 }
 
 // Admission is in arrival order, and a finished request holds its region
@@ -252,20 +292,22 @@ void scheduler(fw_server* s) {
     bool any_busy = false;
     for (auto& b : s->batches) {
       if (!b.busy) continue;
+      if (b.small_pending) {
+        const hipError_t qs = hipEventQuery(b.small_done);
+        if (qs != hipErrorNotReady) {
+          finish(s, b, qs, true);
+          b.small_pending = false;
+        }
+      }
       const hipError_t q = hipEventQuery(b.done);
       if (q == hipErrorNotReady) {
         any_busy = true;
         continue;
       }
-      const uint64_t t = now_ns();
-      for (auto& r : b.reqs) {
-        r->state = (q == hipSuccess) ? kDone : kFailed;
-        if (q != hipSuccess) r->status = FW_EHIP;
-        r->t_done = t;
-      }
+      finish(s, b, q, false);
+      b.small_pending = false;
       b.reqs.clear();
       b.busy = false;
-      s->cv_done.notify_all();
     }
     if (s->stop && s->queue.empty() && !any_busy) break;
     // Admission: one batch per free stream, requests in arrival order.
@@ -284,6 +326,7 @@ void scheduler(fw_server* s) {
           break;
         }
         r->has_region = true;
+        r->small = r->n <= s->opts.small_max_queries;
         r->state = kRunning;
         r->t_admit = now_ns();
         b.reqs.push_back(r);
@@ -344,6 +387,7 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   if (!s->opts.mem_budget_bytes) s->opts.mem_budget_bytes = 1ull << 30;
   if (!s->opts.max_inflight) s->opts.max_inflight = 4;
   if (!s->opts.max_batch_requests) s->opts.max_batch_requests = 256;
+  if (!s->opts.small_max_queries) s->opts.small_max_queries = 2048;
   if (s->opts.max_inflight > 16 || s->opts.max_batch_requests > 4096)
     return fail(FW_EINVAL, "max_inflight <= 16 and max_batch_requests <= 4096");
   for (int a = 0; a < kMaxAlgos; ++a) {
@@ -361,8 +405,9 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   for (auto& b : s->batches) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.small_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc((void**)&b.d_head, kMaxAlgos * 16 * sizeof(uint64_t));
-    for (int a = 0; a < kMaxAlgos && e == hipSuccess; ++a) {
+    for (int a = 0; a < kPhases * kMaxAlgos && e == hipSuccess; ++a) {
       e = hipMalloc((void**)&b.d_desc[a], nd * sizeof(fw::ReqDesc));
       if (e == hipSuccess) e = hipMalloc((void**)&b.d_prefix[a], (nd + 1) * sizeof(uint64_t));
       if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_desc[a], nd * sizeof(fw::ReqDesc), 0);
@@ -484,8 +529,9 @@ int fw_server_destroy(fw_server* s) {
     if (b.stream) (void)hipStreamSynchronize(b.stream);
     if (b.stream) (void)hipStreamDestroy(b.stream);
     if (b.done) (void)hipEventDestroy(b.done);
+    if (b.small_done) (void)hipEventDestroy(b.small_done);
     (void)hipFree(b.d_head);
-    for (int a = 0; a < kMaxAlgos; ++a) {
+    for (int a = 0; a < kPhases * kMaxAlgos; ++a) {
       (void)hipFree(b.d_desc[a]);
       (void)hipFree(b.d_prefix[a]);
       if (b.h_desc[a]) (void)hipHostFree(b.h_desc[a]);

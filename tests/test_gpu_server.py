@@ -48,10 +48,14 @@ def _requests(g, count, seed):
     return reqs
 
 
-def test_mix_equals_alone_and_oracle(env):
+@pytest.mark.parametrize("small_max", [0, 1, 1 << 30])
+def test_mix_equals_alone_and_oracle(env, small_max):
+    """small_max: default split of each batch into small and large requests,
+    every request large, every request small."""
     torch, fw, g, G = env
     reqs = _requests(g, 24, 1)
-    srv = fw.Server(G, mem_budget_bytes=64 << 20, max_inflight=4, max_batch_requests=8)
+    srv = fw.Server(G, mem_budget_bytes=64 << 20, max_inflight=4, max_batch_requests=8,
+                    small_max_queries=small_max)
     try:
         # Submitted from several threads at once, so they mix on the GPU.
         tickets = [None] * len(reqs)
