@@ -521,6 +521,12 @@ def main():
                          "request is the serve workload's own walk")
     ap.add_argument("--queries", type=int, default=0,
                     help="time only the first N queries of the workload (0 = all)")
+    ap.add_argument("--forms", default="",
+                    help="comma-separated extra launches over the same queries after the "
+                         "timed pass, each timed once and its rows compared with the pass's: "
+                         "staged (default staged configuration), staged-WG-DT (workgroup size "
+                         "WG, hub threshold DT), sparse-R (persistent, sparse-N(prev) ratio R), "
+                         "sparse-never")
     ap.add_argument("--large", type=int, default=1,
                     help="also time one persistent pass of the 227M-vertex Chung-Lu node2vec "
                          "workload from all 10M starts (the 'large' record; 0 = skip)")
@@ -659,6 +665,32 @@ def main():
         plain = dict(ms_per_step=ms_p, value=hops / (ms_p / 1e3), identical_paths=same)
         log(f"plain: {ms_p:.1f} ms/step, identical={same}")
 
+    forms = []
+    for spec in [x for x in args.forms.split(",") if x]:
+        parts = spec.split("-")
+        if parts[0] == "staged":
+            mode = "staged"
+            tune = (fw.make_tune(wg_size=int(parts[1]), hub_min=int(parts[2]))
+                    if len(parts) == 3 else None)
+        elif parts[0] == "sparse" and len(parts) == 2:
+            mode = "persistent"
+            tune = fw.make_tune(sparse_ratio=0xFFFFFFFF if parts[1] == "never" else int(parts[1]))
+        else:
+            raise SystemExit(f"unknown form {spec}")
+        out.fill_(-7)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fw.walk(G, algo, prm, starts, L, seed, out=out, mode=mode, stream=stream, async_=True,
+                tune=tune)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fw.sync(G, stream)
+        f_ms = e0.elapsed_time(e1)
+        same = bool(torch.equal(out, paths_main))
+        forms.append(dict(form=spec, ms=f_ms, value=hops / (f_ms / 1e3), identical_paths=same))
+        log(f"form {spec}: {f_ms:.1f} ms, {hops / (f_ms / 1e3) / 1e6:.2f} M steps/s, "
+            f"identical={same}")
+
     host = None
     if args.host_batches:
         L1 = L + 1
@@ -749,6 +781,7 @@ def main():
         "traffic_gbps": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
         "device": device_facts(torch, dev),
         "plain": plain,
+        "forms": forms or None,
         "host_batches": host,
         "cpu_baseline": cpu,
         "latency": latency,
