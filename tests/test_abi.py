@@ -21,7 +21,8 @@ def test_header_declares_entry_points():
     for name in ["fw_graph_upload", "fw_graph_free", "fw_walk", "fw_walk_ex", "fw_sync",
                  "fw_node2vec_factors", "fw_last_error", "fw_graph_info_get", "fw_autotune",
                  "fw_count_steps", "fw_server_create", "fw_server_submit", "fw_server_poll",
-                 "fw_server_wait", "fw_server_destroy"]:
+                 "fw_server_wait", "fw_server_destroy", "fw_walk_noalloc", "fw_walk_host",
+                 "fw_sample_tasks"]:
         assert name in syms
 
 
