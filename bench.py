@@ -337,7 +337,7 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
     head = max(kept, key=lambda r: r["offered_rate_per_s"]) if kept else out[0]
     return dict(workload=workload, mem_budget_bytes=budget,
                 max_inflight=inflight, max_batch_requests=batch,
-                small_max_queries=small or 2048, request_mix=mix_text,
+                small_max_queries=small, request_mix=mix_text,
                 p50_ms=head["p50_ms"], p99_ms=head["p99_ms"],
                 at_rate_per_s=head["offered_rate_per_s"],
                 note="p50/p99 at the highest offered rate the server kept up with",
@@ -513,7 +513,7 @@ def main():
                     help="requests per batch of the server (max_batch_requests, <= 4096)")
     ap.add_argument("--serve-small", type=int, default=0,
                     help="requests of at most this many queries complete in their batch's "
-                         "first phase (0 = the server's default, 2048)")
+                         "first phase (0 = one phase)")
     ap.add_argument("--serve-inflight", type=int, default=4,
                     help="batches the server keeps on the GPU at once (1..16)")
     ap.add_argument("--serve-mix", default="mixed", choices=["mixed", "recipe"],

@@ -109,10 +109,11 @@ struct Request {
 
 constexpr int kMaxAlgos = 4;  // DeepWalk, node2vec, MetaPath, PPR
 
-// A batch runs in two phases on its stream: first one launch per algorithm
-// over its small requests (n <= small_max_queries) and their copies back,
-// then the same for the large ones.  Each phase ends with an event, so small
-// requests complete without waiting for the large ones of their batch.
+// A batch may run in two phases on its stream: first one launch per
+// algorithm over its small requests (n <= small_max_queries, when that is
+// non-zero) and their copies back, then the same for the others.  Each phase
+// ends with an event, so small requests complete without waiting for the
+// large ones of their batch.
 constexpr int kPhases = 2;
 
 struct Batch {
@@ -387,7 +388,6 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   if (!s->opts.mem_budget_bytes) s->opts.mem_budget_bytes = 1ull << 30;
   if (!s->opts.max_inflight) s->opts.max_inflight = 4;
   if (!s->opts.max_batch_requests) s->opts.max_batch_requests = 256;
-  if (!s->opts.small_max_queries) s->opts.small_max_queries = 2048;
   if (s->opts.max_inflight > 16 || s->opts.max_batch_requests > 4096)
     return fail(FW_EINVAL, "max_inflight <= 16 and max_batch_requests <= 4096");
   for (int a = 0; a < kMaxAlgos; ++a) {

@@ -48,10 +48,10 @@ def _requests(g, count, seed):
     return reqs
 
 
-@pytest.mark.parametrize("small_max", [0, 1, 1 << 30])
+@pytest.mark.parametrize("small_max", [0, 2048, 1 << 30])
 def test_mix_equals_alone_and_oracle(env, small_max):
-    """small_max: default split of each batch into small and large requests,
-    every request large, every request small."""
+    """small_max: one phase per batch, batches split into small and large
+    requests, every request small."""
     torch, fw, g, G = env
     reqs = _requests(g, 24, 1)
     srv = fw.Server(G, mem_budget_bytes=64 << 20, max_inflight=4, max_batch_requests=8,
