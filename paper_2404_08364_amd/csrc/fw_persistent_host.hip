@@ -29,11 +29,14 @@ struct GraphKey {
   bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) < 0; }
 };
 
-// A captured launch: its executable graph and the task-pool head counter it
-// owns (captured into the graph, so no other launch ever uses it).
+// A captured launch: its executable graph, the task-pool head counter it
+// owns (captured into the graph, so no other launch ever uses it), and an
+// event recorded after its latest replay (the caller's stream may be gone
+// by the time the entry is dropped; the event is ours).
 struct CachedExec {
   hipGraphExec_t exec = nullptr;
   uint64_t* head = nullptr;
+  hipEvent_t done = nullptr;
   uint64_t last_use = 0;
 };
 
@@ -46,12 +49,16 @@ struct GraphCache {
   uint64_t clock = 0;
 };
 
-void drop_exec(const GraphKey& key, CachedExec& c) {
-  (void)hipStreamSynchronize(key.stream);  // a replay may still be running
-  (void)hipGraphExecDestroy(c.exec);
+void drop_exec(CachedExec& c) {
+  if (c.done) {
+    (void)hipEventSynchronize(c.done);  // the latest replay may still be running
+    (void)hipEventDestroy(c.done);
+  }
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
   (void)hipFree(c.head);
   c.exec = nullptr;
   c.head = nullptr;
+  c.done = nullptr;
 }
 
 // Tuned configurations of both forms, per (graph fingerprint, device,
@@ -195,7 +202,7 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
       auto lru = cache->execs.begin();
       for (auto j = cache->execs.begin(); j != cache->execs.end(); ++j)
         if (j->second.last_use < lru->second.last_use) lru = j;
-      drop_exec(lru->first, lru->second);
+      drop_exec(lru->second);
       cache->execs.erase(lru);
     }
     // The captured launch resets and claims from a counter of its own: a
@@ -203,7 +210,11 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
     // stream at the same time as a replay.
     CachedExec c;
     hipError_t e = hipMalloc((void**)&c.head, kHeadStride * sizeof(uint64_t));
-    if (e != hipSuccess) return e;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      drop_exec(c);
+      return e;
+    }
     LaunchArgs x = a;
     x.head = c.head;
     hipGraph_t graph = nullptr;
@@ -216,13 +227,15 @@ hipError_t launch_persistent_checked(const fw_graph* g, const LaunchArgs& a, hip
     if (e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-      (void)hipFree(c.head);
+      drop_exec(c);
       return e;
     }
     it = cache->execs.emplace(key, c).first;
   }
   it->second.last_use = ++cache->clock;
-  return hipGraphLaunch(it->second.exec, stream);
+  hipError_t e = hipGraphLaunch(it->second.exec, stream);
+  if (e == hipSuccess) e = hipEventRecord(it->second.done, stream);
+  return e;
 }
 
 // Times cfg on the sample: a warm-up launch, then the faster of two timed
@@ -378,7 +391,7 @@ int autotune(fw_graph* g, int algo, const DevParams& dp, const uint32_t* starts,
 void release_graph_state(fw_graph* g) {
   auto* cache = static_cast<GraphCache*>(g->graph_cache);
   if (!cache) return;
-  for (auto& kv : cache->execs) drop_exec(kv.first, kv.second);
+  for (auto& kv : cache->execs) drop_exec(kv.second);
   delete cache;
   g->graph_cache = nullptr;
 }
