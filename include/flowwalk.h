@@ -340,7 +340,8 @@ int fw_sync(const fw_graph* g, void* stream);
 /* ------------------------------------------------------------------------
  * Served form: continuous batching of walk requests (graph and in-flight
  * walks resident in HBM).  Requests are admitted in arrival order while
- * their device memory, n * 4 + n * (length + 1) * 4 bytes (rounded up to 256),
+ * their device memory, a 256-byte hop counter plus n * 4 bytes of start
+ * vertices (rounded up to 256) plus n * (length + 1) * 4 bytes of rows,
  * fits in mem_budget_bytes (the per-request form of Eq. 5's rule that
  * result memory bounds the batch, section 5.2).  Admitted requests run as
  * multi-request persistent launches on up to max_inflight streams at once,
@@ -392,9 +393,11 @@ int fw_server_poll(fw_server* s, uint64_t ticket);
  * entries to out_host (host, may be NULL), fills *stats (may be NULL), and
  * releases the request and its memory.  Returns the request's status
  * (FW_ECANCELED if the server shut down first).  Requests may be waited for
- * in any order: a finished request keeps its device region until it is
- * collected, unless the next request in arrival order needs the memory, in
- * which case its rows move to host memory (held until the wait). */
+ * in any order: a finished request gives its device memory back at once and
+ * keeps its rows in the server's pinned host staging (twice
+ * mem_budget_bytes) until it is collected; when the next request in arrival
+ * order finds no staging left, uncollected rows move to ordinary host
+ * memory (held until the wait). */
 int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_stats* stats);
 
 /* Stops admitting, cancels queued requests (FW_ECANCELED), waits for

@@ -39,7 +39,7 @@ uint64_t now_ns() {
 }
 
 // First-fit allocator over [0, size) with coalescing (host bookkeeping of the
-// device arena and its pinned mirror).
+// device arena and of the pinned host staging arena).
 class Arena {
  public:
   explicit Arena(uint64_t size) : size_(size) { free_[0] = size; }
@@ -94,8 +94,10 @@ struct Request {
   uint64_t n;
   uint32_t length;
   uint64_t seed;
-  uint64_t bytes = 0, off = 0;  // arena region: starts then rows
-  bool has_region = false;
+  uint64_t bytes = 0;
+  uint64_t off = 0, hoff = 0;   // device region and its pinned host staging region
+  bool has_region = false;      // device region held (until the rows are copied back)
+  bool has_host = false;        // host region held (until the request is collected)
   ReqState state = kQueued;
   int status = FW_OK;
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
@@ -139,8 +141,8 @@ struct fw_server {
   fw_server_opts opts{};
   fw::TuneCfg cfg[kMaxAlgos];
   uint8_t* d_arena = nullptr;
-  uint8_t* h_arena = nullptr;  // pinned mirror (same offsets)
-  std::unique_ptr<Arena> arena;
+  uint8_t* h_arena = nullptr;  // pinned host staging, twice the device budget
+  std::unique_ptr<Arena> arena, host_arena;
   std::vector<Batch> batches;
   uint32_t* d_status = nullptr;
 
@@ -174,7 +176,7 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
   hipError_t e = hipSuccess;
   for (auto& r : b.reqs) {
     // The counter starts at zero and goes over with the start vertices.
-    uint8_t* h = s->h_arena + r->off;
+    uint8_t* h = s->h_arena + r->hoff;
     std::memset(h, 0, kCounterBytes);
     std::memcpy(h + kCounterBytes, r->starts.data(), r->n * 4);
     e = hipMemcpyAsync(s->d_arena + r->off, h, kCounterBytes + r->n * 4, hipMemcpyHostToDevice,
@@ -231,10 +233,10 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
     for (auto& r : b.reqs) {
       if (r->small != small) continue;
       const uint64_t so = kCounterBytes + starts_bytes(r->n);
-      e = hipMemcpyAsync(s->h_arena + r->off + so, s->d_arena + r->off + so,
+      e = hipMemcpyAsync(s->h_arena + r->hoff + so, s->d_arena + r->off + so,
                          r->n * ((uint64_t)r->length + 1) * 4, hipMemcpyDeviceToHost, b.stream);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(s->h_arena + r->off, s->d_arena + r->off, sizeof(uint64_t),
+        e = hipMemcpyAsync(s->h_arena + r->hoff, s->d_arena + r->off, sizeof(uint64_t),
                            hipMemcpyDeviceToHost, b.stream);
       if (e != hipSuccess) return e;
     }
@@ -256,30 +258,37 @@ void finish(fw_server* s, Batch& b, hipError_t q, bool small_only) {
     r->state = (q == hipSuccess) ? kDone : kFailed;
     if (q != hipSuccess) r->status = FW_EHIP;
     r->t_done = t;
+    // The event covered the copy back: the device region is free again.
+    if (r->has_region) {
+      s->arena->release(r->off);
+      r->has_region = false;
+    }
   }
   s->cv_done.notify_all();
 }
 
-// Admission is in arrival order, and a finished request holds its region
-// until it is waited for.  When the next request does not fit, finished
-// requests nobody has collected yet move their rows to host memory and give
-// their regions back, so that the order of the client's waits cannot stall
-// admission.  Returns whether any region was freed.  (Lock held.)
+// A finished request gives its device region back at once (its rows are in
+// its host region by then) and keeps its host region until it is waited
+// for.  Admission is in arrival order; when the next request finds no host
+// region, finished requests nobody has collected yet move their rows to
+// ordinary host memory and give their host regions back, so that the order
+// of the client's waits cannot stall admission.  Returns whether any region
+// was freed.  (Lock held.)
 bool spill_finished(fw_server* s) {
   bool freed = false;
   for (auto& kv : s->reqs) {
     auto& r = kv.second;
-    if (!r->has_region || (r->state != kDone && r->state != kFailed)) continue;
+    if (!r->has_host || (r->state != kDone && r->state != kFailed)) continue;
     if (r->state == kDone) {
       const uint64_t so = kCounterBytes + starts_bytes(r->n);
       const uint64_t cells = r->n * ((uint64_t)r->length + 1);
       r->spill.resize(cells);
-      std::memcpy(r->spill.data(), s->h_arena + r->off + so, cells * 4);
-      std::memcpy(&r->spill_steps, s->h_arena + r->off, sizeof(uint64_t));
+      std::memcpy(r->spill.data(), s->h_arena + r->hoff + so, cells * 4);
+      std::memcpy(&r->spill_steps, s->h_arena + r->hoff, sizeof(uint64_t));
       r->spilled = true;
     }
-    s->arena->release(r->off);
-    r->has_region = false;
+    s->host_arena->release(r->hoff);
+    r->has_host = false;
     freed = true;
   }
   return freed;
@@ -322,11 +331,14 @@ void scheduler(fw_server* s) {
           s->queue.pop_front();
           continue;
         }
-        if (!s->arena->alloc(r->bytes, &r->off)) {
+        if (!s->arena->alloc(r->bytes, &r->off)) break;  // wait for completions
+        if (!s->host_arena->alloc(r->bytes, &r->hoff)) {
+          s->arena->release(r->off);
           if (spill_finished(s)) continue;
           break;
         }
         r->has_region = true;
+        r->has_host = true;
         r->small = r->n <= s->opts.small_max_queries;
         r->state = kRunning;
         r->t_admit = now_ns();
@@ -371,6 +383,10 @@ void release_request(fw_server* s, const std::shared_ptr<Request>& r) {
     s->arena->release(r->off);
     r->has_region = false;
   }
+  if (r->has_host) {
+    s->host_arena->release(r->hoff);
+    r->has_host = false;
+  }
   s->reqs.erase(r->ticket);
   s->cv_sched.notify_one();
 }
@@ -397,7 +413,7 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   }
   hipError_t e = hipSetDevice(g->device);
   if (e == hipSuccess) e = hipMalloc((void**)&s->d_arena, s->opts.mem_budget_bytes);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_arena, s->opts.mem_budget_bytes, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_arena, 2 * s->opts.mem_budget_bytes, 0);
   if (e == hipSuccess) e = hipMalloc((void**)&s->d_status, 256);
   if (e == hipSuccess) e = hipMemset(s->d_status, 0, 256);
   s->batches.resize(s->opts.max_inflight);
@@ -421,6 +437,7 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
     return fail(e == hipErrorOutOfMemory ? FW_ENOMEM : FW_EHIP, "creating the server");
   }
   s->arena = std::make_unique<Arena>(s->opts.mem_budget_bytes);
+  s->host_arena = std::make_unique<Arena>(2 * s->opts.mem_budget_bytes);
   fw_server* raw = s.release();
   raw->thread = std::thread(scheduler, raw);
   *out = raw;
@@ -486,8 +503,8 @@ int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_sta
     stats->steps = 0;
     if (r->status == FW_OK && r->spilled)
       stats->steps = r->spill_steps;
-    else if (r->status == FW_OK && r->has_region)
-      std::memcpy(&stats->steps, s->h_arena + r->off, sizeof(uint64_t));
+    else if (r->status == FW_OK && r->has_host)
+      std::memcpy(&stats->steps, s->h_arena + r->hoff, sizeof(uint64_t));
   }
   int rc = r->status;
   if (rc == FW_OK && out_host) {
@@ -495,7 +512,7 @@ int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_sta
     if (r->spilled)
       std::memcpy(out_host, r->spill.data(), cells * 4);
     else
-      std::memcpy(out_host, s->h_arena + r->off + kCounterBytes + starts_bytes(r->n), cells * 4);
+      std::memcpy(out_host, s->h_arena + r->hoff + kCounterBytes + starts_bytes(r->n), cells * 4);
   }
   release_request(s, r);
   if (rc != FW_OK) return fail(rc, rc == FW_ECANCELED ? "request cancelled" : "request failed");
