@@ -216,7 +216,7 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
 def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
                 budget: int, log, mix: str = "mixed", graph=None, inflight: int = 4,
                 ceiling_requests: int = 4000, check_every: int = 64, batch: int = 512,
-                small: int = 0):
+                small: int = 0, express: int = 0):
     """Poisson request streams against the served form, one per offered rate
     (each for `seconds` of arrivals, capped at `max_requests` requests);
     returns latency and throughput per rate, and the served form's ceiling
@@ -262,7 +262,8 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
         starts_all = synth.uniform_ids(int(sizes.sum()), g.n_vertices, 77 + k)
         offs = np.concatenate([[0], np.cumsum(sizes)])
         srv = fw.Server(G, mem_budget_bytes=budget, max_inflight=inflight,
-                        max_batch_requests=batch, small_max_queries=small)
+                        max_batch_requests=batch, small_max_queries=small,
+                        express_max_queries=express)
         tickets = [None] * n_req
         sched_ns = [0] * n_req
         lat = np.zeros(n_req)
@@ -337,7 +338,7 @@ def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: i
     head = max(kept, key=lambda r: r["offered_rate_per_s"]) if kept else out[0]
     return dict(workload=workload, mem_budget_bytes=budget,
                 max_inflight=inflight, max_batch_requests=batch,
-                small_max_queries=small, request_mix=mix_text,
+                small_max_queries=small, express_max_queries=express, request_mix=mix_text,
                 p50_ms=head["p50_ms"], p99_ms=head["p99_ms"],
                 at_rate_per_s=head["offered_rate_per_s"],
                 note="p50/p99 at the highest offered rate the server kept up with",
@@ -514,6 +515,13 @@ def main():
     ap.add_argument("--serve-small", type=int, default=0,
                     help="requests of at most this many queries complete in their batch's "
                          "first phase (0 = one phase)")
+    ap.add_argument("--serve-express", type=int, default=0,
+                    help="requests of at most this many queries may take the server's "
+                         "express lane (0 = none)")
+    ap.add_argument("--serve-variants", default="",
+                    help="comma-separated server settings B:F:S:E (requests per batch, "
+                         "batches in flight, small_max_queries, express_max_queries) run "
+                         "after the main serve phase on the same graph and request streams")
     ap.add_argument("--serve-inflight", type=int, default=4,
                     help="batches the server keeps on the GPU at once (1..16)")
     ap.add_argument("--serve-mix", default="mixed", choices=["mixed", "recipe"],
@@ -738,10 +746,29 @@ def main():
         torch.cuda.empty_cache()
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         same = (g, G) if args.serve_workload == args.workload else None
+        if same is None and args.serve_variants:
+            sg = synth.load_recipe_graph(args.serve_workload)
+            same = (sg, fw.Graph.of(sg))
         latency = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
                               args.serve_max_requests, 4 << 30, log, args.serve_mix, same,
                               args.serve_inflight, args.serve_ceiling, batch=args.serve_batch,
-                              small=args.serve_small)
+                              small=args.serve_small, express=args.serve_express)
+        # Other server settings on the same graph and request streams.
+        variants = []
+        for spec in [x for x in args.serve_variants.split(",") if x]:
+            vb, vf, vs, ve = (int(x) for x in spec.split(":"))
+            r = serve_phase(fw, synth, args.serve_workload, rates, args.serve_seconds,
+                            args.serve_max_requests, 4 << 30, log, args.serve_mix, same, vf,
+                            args.serve_ceiling, 0, batch=vb, small=vs, express=ve)
+            variants.append(dict(max_batch_requests=vb, max_inflight=vf, small_max_queries=vs,
+                                 express_max_queries=ve,
+                                 ceiling_steps_per_s=(r["ceiling"] or {}).get("served_steps_per_s"),
+                                 sweep=[{k: x[k] for k in ("offered_rate_per_s", "p50_ms", "p99_ms",
+                                                           "served_steps_per_s", "keeps_up")}
+                                        for x in r["sweep"]]))
+            log(f"serve variant {spec}: {variants[-1]}")
+        if variants:
+            latency["variants"] = variants
 
     large = None
     if args.large and args.workload != "chunglu227m_n2v":

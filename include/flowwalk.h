@@ -361,6 +361,11 @@ typedef struct fw_server_opts {
                                   requests (default 0: one phase; on the
                                   R-MAT-24 mix a split at 2048 raised p50 and
                                   p99 at 1000 requests/s) */
+  uint32_t express_max_queries; /* non-zero: one of the max_inflight streams is
+                                  an express lane for requests of at most this
+                                  many queries (taken from anywhere in the
+                                  queue), with 2 workgroups per CU kept for it;
+                                  the other streams share the rest (default 0) */
 } fw_server_opts;
 
 typedef struct fw_req_stats {

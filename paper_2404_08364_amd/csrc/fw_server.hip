@@ -118,7 +118,11 @@ constexpr int kMaxAlgos = 4;  // DeepWalk, node2vec, MetaPath, PPR
 // large ones of their batch.
 constexpr int kPhases = 2;
 
+// Workgroups per CU reserved for the express lane (fw_server_opts).
+constexpr uint32_t kExpressWgs = 2;
+
 struct Batch {
+  bool express = false;  // the express lane: small requests, a reserved share of the CUs
   std::vector<std::shared_ptr<Request>> reqs;
   hipEvent_t done = nullptr;        // end of the last phase
   hipEvent_t small_done = nullptr;  // end of the small-request phase
@@ -220,6 +224,15 @@ hipError_t launch_batch(fw_server* s, Batch& b) {
       if (e != hipSuccess) return e;
       fw::ReqTable t{b.d_desc[ta], b.d_prefix[ta], k, total};
       fw::TuneCfg cfg = s->cfg[a];
+      if (s->opts.express_max_queries) {
+        // The express lane keeps kExpressWgs workgroups per CU for itself;
+        // the bulk streams share the rest, so an express launch always finds
+        // room instead of waiting for persistent launches to drain.
+        const uint32_t bulk = s->opts.max_inflight - 1;
+        const uint32_t w = b.express ? kExpressWgs
+                                     : std::max<uint32_t>(1, (cfg.wgs_per_cu - kExpressWgs) / bulk);
+        cfg.wgs_per_cu = std::min(cfg.wgs_per_cu, w);
+      }
       cfg.narrow = 1;
       for (uint32_t i = 0; i < k; ++i)
         cfg.narrow &= fw::narrow_products(s->g->max_w, b.h_desc[ta][i].prm);
@@ -320,15 +333,16 @@ void scheduler(fw_server* s) {
       b.busy = false;
     }
     if (s->stop && s->queue.empty() && !any_busy) break;
-    // Admission: one batch per free stream, requests in arrival order.
+    // Admission: one batch per free stream, requests in arrival order (the
+    // express lane takes the small requests among them, wherever they are
+    // in the queue).
     for (auto& b : s->batches) {
-      if (b.busy || s->queue.empty()) continue;
-      while (!s->queue.empty() && b.reqs.size() < s->opts.max_batch_requests) {
-        auto r = s->queue.front();
-        if (s->stop) {
-          r->state = kFailed;
-          r->status = FW_ECANCELED;
-          s->queue.pop_front();
+      if (b.busy || s->queue.empty() || s->stop) continue;
+      auto it = s->queue.begin();
+      while (it != s->queue.end() && b.reqs.size() < s->opts.max_batch_requests) {
+        auto r = *it;
+        if (b.express && r->n > s->opts.express_max_queries) {
+          ++it;
           continue;
         }
         if (!s->arena->alloc(r->bytes, &r->off)) break;  // wait for completions
@@ -343,7 +357,7 @@ void scheduler(fw_server* s) {
         r->state = kRunning;
         r->t_admit = now_ns();
         b.reqs.push_back(r);
-        s->queue.pop_front();
+        it = s->queue.erase(it);
       }
       if (b.reqs.empty()) continue;
       b.busy = true;
@@ -406,6 +420,8 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   if (!s->opts.max_batch_requests) s->opts.max_batch_requests = 256;
   if (s->opts.max_inflight > 16 || s->opts.max_batch_requests > 4096)
     return fail(FW_EINVAL, "max_inflight <= 16 and max_batch_requests <= 4096");
+  if (s->opts.express_max_queries && s->opts.max_inflight < 2)
+    return fail(FW_EINVAL, "an express lane needs max_inflight >= 2");
   for (int a = 0; a < kMaxAlgos; ++a) {
     bool staged = false;
     const int rc = fw::resolve_tune(g, a, FW_MODE_PERSISTENT, nullptr, &s->cfg[a], &staged);
@@ -417,6 +433,7 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   if (e == hipSuccess) e = hipMalloc((void**)&s->d_status, 256);
   if (e == hipSuccess) e = hipMemset(s->d_status, 0, 256);
   s->batches.resize(s->opts.max_inflight);
+  if (s->opts.express_max_queries) s->batches[0].express = true;
   const size_t nd = s->opts.max_batch_requests;
   for (auto& b : s->batches) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);

@@ -71,7 +71,8 @@ class BatchOpts(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
-                ("max_batch_requests", ctypes.c_uint32), ("small_max_queries", ctypes.c_uint32)]
+                ("max_batch_requests", ctypes.c_uint32), ("small_max_queries", ctypes.c_uint32),
+                ("express_max_queries", ctypes.c_uint32)]
 
 
 class ReqStats(ctypes.Structure):
@@ -368,9 +369,11 @@ class Server:
     returns the uint32 paths [n, length + 1] and the request's timestamps."""
 
     def __init__(self, graph: Graph, mem_budget_bytes: int = 1 << 30, max_inflight: int = 4,
-                 max_batch_requests: int = 256, small_max_queries: int = 0):
+                 max_batch_requests: int = 256, small_max_queries: int = 0,
+                 express_max_queries: int = 0):
         self.graph = graph
-        o = ServerOpts(mem_budget_bytes, max_inflight, max_batch_requests, small_max_queries)
+        o = ServerOpts(mem_budget_bytes, max_inflight, max_batch_requests, small_max_queries,
+                       express_max_queries)
         h = ctypes.c_void_p()
         _check(_lib.fw_server_create(graph.handle, ctypes.byref(o), ctypes.byref(h)),
                "fw_server_create")

@@ -48,14 +48,16 @@ def _requests(g, count, seed):
     return reqs
 
 
-@pytest.mark.parametrize("small_max", [0, 2048, 1 << 30])
-def test_mix_equals_alone_and_oracle(env, small_max):
+@pytest.mark.parametrize("small_max,express", [(0, 0), (2048, 0), (1 << 30, 0), (0, 500),
+                                               (0, 1 << 30)])
+def test_mix_equals_alone_and_oracle(env, small_max, express):
     """small_max: one phase per batch, batches split into small and large
-    requests, every request small."""
+    requests, every request small; express: no express lane, one for the
+    requests of at most 500 queries, one every request may take."""
     torch, fw, g, G = env
     reqs = _requests(g, 24, 1)
     srv = fw.Server(G, mem_budget_bytes=64 << 20, max_inflight=4, max_batch_requests=8,
-                    small_max_queries=small_max)
+                    small_max_queries=small_max, express_max_queries=express)
     try:
         # Submitted from several threads at once, so they mix on the GPU.
         tickets = [None] * len(reqs)
