@@ -214,7 +214,7 @@ def cpu_baseline(g, algo, oprm, starts, L, seed, n, target_s, gpu_rows_fn):
 
 
 def serve_phase(fw, synth, workload: str, rates, seconds: float, max_requests: int,
-                budget: int, log, mix: str = "mixed", graph=None, inflight: int = 4,
+                budget: int, log, mix: str = "mixed", graph=None, inflight: int = 3,
                 ceiling_requests: int = 4000, check_every: int = 64, batch: int = 512,
                 small: int = 0, express: int = 0):
     """Poisson request streams against the served form, one per offered rate
@@ -522,7 +522,7 @@ def main():
                     help="comma-separated server settings B:F:S:E (requests per batch, "
                          "batches in flight, small_max_queries, express_max_queries) run "
                          "after the main serve phase on the same graph and request streams")
-    ap.add_argument("--serve-inflight", type=int, default=4,
+    ap.add_argument("--serve-inflight", type=int, default=3,
                     help="batches the server keeps on the GPU at once (1..16)")
     ap.add_argument("--serve-mix", default="mixed", choices=["mixed", "recipe"],
                     help="mixed: DeepWalk / node2vec / MetaPath requests; recipe: every "

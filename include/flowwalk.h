@@ -353,7 +353,7 @@ typedef struct fw_server fw_server;
 
 typedef struct fw_server_opts {
   uint64_t mem_budget_bytes;   /* device bytes for request buffers (default 1 GiB) */
-  uint32_t max_inflight;       /* concurrent batches / streams (default 4, <= 16) */
+  uint32_t max_inflight;       /* concurrent batches / streams (default 3, <= 16) */
   uint32_t max_batch_requests; /* requests per batch (default 256, <= 4096) */
   uint32_t small_max_queries;  /* non-zero: requests of at most this many
                                   queries run in their batch's first phase and

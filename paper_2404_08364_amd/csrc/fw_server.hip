@@ -416,7 +416,7 @@ int fw_server_create(const fw_graph* g, const fw_server_opts* opts, fw_server** 
   s->g = g;
   if (opts) s->opts = *opts;
   if (!s->opts.mem_budget_bytes) s->opts.mem_budget_bytes = 1ull << 30;
-  if (!s->opts.max_inflight) s->opts.max_inflight = 4;
+  if (!s->opts.max_inflight) s->opts.max_inflight = 3;
   if (!s->opts.max_batch_requests) s->opts.max_batch_requests = 256;
   if (s->opts.max_inflight > 16 || s->opts.max_batch_requests > 4096)
     return fail(FW_EINVAL, "max_inflight <= 16 and max_batch_requests <= 4096");

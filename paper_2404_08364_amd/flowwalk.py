@@ -368,7 +368,7 @@ class Server:
     submit() takes host start vertices (numpy) and returns a ticket; wait()
     returns the uint32 paths [n, length + 1] and the request's timestamps."""
 
-    def __init__(self, graph: Graph, mem_budget_bytes: int = 1 << 30, max_inflight: int = 4,
+    def __init__(self, graph: Graph, mem_budget_bytes: int = 1 << 30, max_inflight: int = 3,
                  max_batch_requests: int = 256, small_max_queries: int = 0,
                  express_max_queries: int = 0):
         self.graph = graph
