@@ -102,8 +102,8 @@ struct Request {
   int status = FW_OK;
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
   bool small = false;  // runs in its batch's first phase
-  // A finished request whose region was reclaimed before it was waited for
-  // keeps its rows and hop count here.
+  // A finished request whose host region was reclaimed before it was waited
+  // for keeps its rows and hop count here.
   bool spilled = false;
   std::vector<uint32_t> spill;
   uint64_t spill_steps = 0;
