@@ -16,7 +16,7 @@
 //
 // Node2vec membership in N(prev) for non-tiny hops uses the wavefront's LDS
 // region: an exact 4-cell-bucket hash set of N(prev) when it fits; otherwise,
-// while N(prev) is at most 16x N(cur), a merge of the two sorted rows (each
+// while N(prev) is at most 64x N(cur), a merge of the two sorted rows (each
 // 256-entry chunk of N(cur) stages the window of N(prev) that holds its value
 // range into LDS and searches it there); when N(prev) is much larger than
 // N(cur), binary search of the sorted row in global memory.  No global memory
@@ -44,6 +44,13 @@ constexpr int kGroups = 4;  // queries per wavefront
 // Node2vec hops from vertices of at least this degree may take the
 // sparse-N(prev) pass (sparse_prev_group_totals).
 constexpr uint64_t kSparseMinDegree = 2048;
+// A node2vec hop whose N(prev) is more than this many times longer than
+// N(cur) looks each of N(cur)'s keys up by binary search of N(prev) in global
+// memory (few keys; the top levels of a hub's row stay in cache); a shorter
+// N(prev) goes to the hash set or the merge.  Full passes on one MI355X for
+// ratios 16, 32, 64 and 128: R-MAT-22 node2vec 1308, 1272, 1275 and
+// 1330 ms; Chung-Lu 227M node2vec, 1M queries, 7157, 7084, 7021 and 6992 ms.
+constexpr uint64_t kSearchRatio = 64;
 constexpr int kGroupLanes = 16;
 constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
 
@@ -142,9 +149,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 __device__ __forceinline__ void build_table(Table& tb, const uint32_t* __restrict__ adj,
                                             uint64_t d, int lane, bool allow_merge = true) {
   tb.kind = 0;
-  // Past 16x, searching for the few keys reads less than the build or the
-  // merge (16 against 8, 32 and 64 measured on R-MAT-22 node2vec).
-  if (tb.pd == 0 || tb.pd > 16 * d) return;
+  if (tb.pd == 0 || tb.pd > kSearchRatio * d) return;
   if (2 * tb.pd > tb.cells) {
     // Too large for the hash set: merge the sorted rows (the region must
     // hold at least one 256-entry staging round).

@@ -408,6 +408,38 @@ def test_merge_membership_windows(env, cells, d):
            tune=fw.make_tune(hash_cells=cells, tiny_max=1))
 
 
+def _ratio_boundary(dc, pd):
+    """Hub 0 with pd neighbours, 64 of them the vertices 1..64 of degree dc:
+    the hub plus dc - 1 others, half of those also neighbours of the hub.
+    Heavy edges send walks hub -> vertex k -> hub -> vertex j, so the hops
+    from vertex j test N(cur), dc entries, against the hub's pd."""
+    rng = np.random.default_rng(pd * 131 + dc)
+    hub_others = 65 + np.arange(pd - 64)
+    nonshared = 65 + (pd - 64) + np.arange(4 * dc)
+    edges = [(0, k, 50_000, 0) for k in range(1, 65)]
+    edges += [(0, int(v), 1, 0) for v in hub_others]
+    for k in range(1, 65):
+        sh = rng.choice(hub_others, (dc - 1) // 2, replace=False)
+        ns = rng.choice(nonshared, dc - 1 - len(sh), replace=False)
+        edges += [(k, int(v), int(rng.integers(1, 1000)), 0) for v in np.concatenate([sh, ns])]
+    return csr_from_edges(65 + (pd - 64) + 4 * dc, edges, labels=False)
+
+
+@pytest.mark.parametrize("cells", [1024, 4096])
+@pytest.mark.parametrize("pd", [1280, 1281])
+def test_node2vec_search_ratio_boundary(env, cells, pd):
+    """N(prev) at 64x N(cur) (merge with 1,024 cells, hash set with 4,096)
+    and one entry past it (binary search in global memory): the same walks
+    as the oracle on both sides of the switch."""
+    torch, fw = env
+    g = _ratio_boundary(20, pd)
+    assert int(g.offsets[1] - g.offsets[0]) == pd and int(g.offsets[2] - g.offsets[1]) == 20
+    starts = np.tile(np.arange(1, 65, dtype=np.uint32), 4)
+    for f in [(4, 2, 1), (1, 2, 4)]:
+        _check(env, g, "node2vec", f, (), starts, 12, 2024, "persistent",
+               tune=fw.make_tune(hash_cells=cells, sparse_ratio=0xFFFFFFFF))
+
+
 def _hub_with_parallel_edges(weighted):
     """Hub 0 with 3,000 leaves, parallel edges to 5 (three) and 7 (two), and a
     self-loop; vertex 5 has parallel edges to 8, a self-loop, and edges to 6
