@@ -402,7 +402,9 @@ int fw_server_poll(fw_server* s, uint64_t ticket);
  * keeps its rows in the server's pinned host staging (twice
  * mem_budget_bytes) until it is collected; when the next request in arrival
  * order finds no staging left, uncollected rows move to ordinary host
- * memory (held until the wait). */
+ * memory (held until the wait).  A ticket is waited for once: another wait
+ * for it, also one from another thread while the first blocks, returns
+ * FW_EINVAL. */
 int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_stats* stats);
 
 /* Stops admitting, cancels queued requests (FW_ECANCELED), waits for

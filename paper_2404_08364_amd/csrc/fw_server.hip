@@ -102,6 +102,7 @@ struct Request {
   int status = FW_OK;
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
   bool small = false;  // runs in its batch's first phase
+  bool claimed = false;  // a wait has taken the ticket
   // A finished request whose host region was reclaimed before it was waited
   // for keeps its rows and hop count here.
   bool spilled = false;
@@ -506,6 +507,10 @@ int fw_server_wait(fw_server* s, uint64_t ticket, uint32_t* out_host, fw_req_sta
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(FW_EINVAL, "unknown ticket");
   std::shared_ptr<Request> r = it->second;
+  // One wait per ticket: a second one would read rows whose memory the
+  // first gives back.
+  if (r->claimed) return fail(FW_EINVAL, "ticket is already being waited for");
+  r->claimed = true;
   ++s->waiters;
   s->cv_done.wait(lk, [&] { return r->state == kDone || r->state == kFailed; });
   --s->waiters;

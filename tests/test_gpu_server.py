@@ -135,3 +135,34 @@ def test_shutdown_cancels_queued(env):
     srv.close()  # queued ones are cancelled, launched ones finish
     # The handle is gone: nothing more to wait on; the call must not hang.
     assert len(tickets) == 20
+
+
+def test_one_wait_per_ticket(env):
+    """Two threads wait for the same ticket through the C ABI: one gets the
+    rows (equal to the oracle's), the other FW_EINVAL (the ticket is taken,
+    or already released), and neither reads memory the other gave back."""
+    import ctypes
+    torch, fw, g, G = env
+    srv = fw.Server(G, mem_budget_bytes=1 << 26)
+    try:
+        st = np.arange(3000, dtype=np.uint32)
+        prm = fw.make_params((1, 2, 4))
+        t = srv.submit("node2vec", prm, st, 80, 77)
+        outs = [np.zeros((3000, 81), dtype=np.uint32) for _ in range(2)]
+        rcs = [None, None]
+
+        def wait(i):
+            stats = fw.ReqStats()
+            rcs[i] = fw._lib.fw_server_wait(srv._h, t, outs[i].ctypes.data, ctypes.byref(stats))
+
+        th = [threading.Thread(target=wait, args=(i,)) for i in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join(timeout=60)
+        assert sorted(rcs) == sorted([fw.OK, fw.EINVAL]), rcs
+        got = outs[rcs.index(fw.OK)]
+        assert_rows_equal(got, oracle.walk(g, "node2vec", oracle.params(1, 2, 4), st, 80, 77),
+                          "the one wait")
+    finally:
+        srv.close()
