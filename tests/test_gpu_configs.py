@@ -30,23 +30,28 @@ def _sample_ids(starts, deg, n_strided, n_top):
     return np.unique(np.concatenate([strided, top]))
 
 
+def _walk_params(fw, walk):
+    """The library's and the oracle's parameters of a recipe's walk."""
+    algo = walk["algo"]
+    if algo == "node2vec":
+        (pn, pd), (qn, qd) = walk["p"], walk["q"]
+        f = fw.node2vec_factors(pn, pd, qn, qd)
+        return algo, fw.make_params(f), oracle.params(*f)
+    if algo == "metapath":
+        return algo, fw.make_params(schema=walk["schema"]), oracle.params(schema=walk["schema"])
+    if algo == "ppr":
+        stop = tuple(walk["stop"])
+        return algo, fw.make_params(stop=stop), oracle.params(stop=stop)
+    return algo, None, oracle.params()
+
+
 def _run(recipe, mode, n_strided, n_top, tune=True):
     torch = torch_or_skip()
     from paper_2404_08364_amd import flowwalk as fw
     g = synth.load_recipe_graph(recipe)
     walk = synth.RECIPES[recipe]["walk"]
-    algo, L, seed = walk["algo"], walk["length"], walk["seed"]
-    if algo == "node2vec":
-        (pn, pd), (qn, qd) = walk["p"], walk["q"]
-        f = fw.node2vec_factors(pn, pd, qn, qd)
-        prm, oprm = fw.make_params(f), oracle.params(*f)
-    elif algo == "metapath":
-        prm, oprm = fw.make_params(schema=walk["schema"]), oracle.params(schema=walk["schema"])
-    elif algo == "ppr":
-        stop = tuple(walk["stop"])
-        prm, oprm = fw.make_params(stop=stop), oracle.params(stop=stop)
-    else:
-        prm, oprm = None, oracle.params()
+    L, seed = walk["length"], walk["seed"]
+    algo, prm, oprm = _walk_params(fw, walk)
     starts = synth.recipe_starts(recipe, g)
     G = fw.Graph.of(g)
     st = torch.from_numpy(starts.view(np.int32)).cuda()
@@ -93,32 +98,30 @@ def test_rmat22_ppr_full_size():
 
 
 @pytest.mark.skipif(os.environ.get("FW_FULL_PARITY") != "1",
-                    reason="all 4,194,304 rows take about 11 minutes of oracle time on 16 "
-                           "host threads; run with FW_FULL_PARITY=1")
-def test_rmat22_node2vec_all_rows():
-    """Every row of the R-MAT-22 node2vec workload (4,194,304 queries, 80 hops)
-    against the oracle, in slices of 65,536 queries (progress on stdout)."""
+                    reason="all 4,194,304 rows take minutes of oracle time on 16 host "
+                           "threads (node2vec about 11); run with FW_FULL_PARITY=1")
+@pytest.mark.parametrize("recipe", ["rmat22_n2v", "rmat22_deepwalk", "rmat22_ppr"])
+def test_rmat22_all_rows(recipe):
+    """Every row of an R-MAT-22 workload (4,194,304 queries, up to 80 hops)
+    in the bench's launch configuration against the oracle, in slices of
+    65,536 queries (progress on stdout)."""
     torch = torch_or_skip()
     from paper_2404_08364_amd import flowwalk as fw
-    recipe = "rmat22_n2v"
     g = synth.load_recipe_graph(recipe)
     walk = synth.RECIPES[recipe]["walk"]
-    (pn, pd), (qn, qd) = walk["p"], walk["q"]
-    f = fw.node2vec_factors(pn, pd, qn, qd)
+    algo, prm, oprm = _walk_params(fw, walk)
     L, seed = walk["length"], walk["seed"]
     starts = synth.recipe_starts(recipe, g)
     G = fw.Graph.of(g)
     st = torch.from_numpy(starts.view(np.int32)).cuda()
-    fw.autotune(G, "node2vec", fw.make_params(f), st[:: max(1, len(starts) // 65536)].contiguous(),
-                L, seed)
-    got = fw.walk(G, "node2vec", fw.make_params(f), st, L, seed, mode="persistent")
+    fw.autotune(G, algo, prm, st[:: max(1, len(starts) // 65536)].contiguous(), L, seed)
+    got = fw.walk(G, algo, prm, st, L, seed, mode="persistent")
     torch.cuda.synchronize()
     got = got.cpu().numpy().view(np.uint32)
     G.free()
-    oprm = oracle.params(*f)
     n = starts.shape[0]
     for lo in range(0, n, 65536):
         qids = np.arange(lo, min(n, lo + 65536), dtype=np.uint64)
-        exp = oracle.walk_ids_threaded(g, "node2vec", oprm, starts, qids, L, seed, THREADS)
+        exp = oracle.walk_ids_threaded(g, algo, oprm, starts, qids, L, seed, THREADS)
         assert_rows_equal(got[lo: lo + len(qids)], exp, f"{recipe} rows {lo}..")
         print(f"rows {lo + len(qids)}/{n} identical", flush=True)
