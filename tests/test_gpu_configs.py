@@ -98,13 +98,15 @@ def test_rmat22_ppr_full_size():
 
 
 @pytest.mark.skipif(os.environ.get("FW_FULL_PARITY") != "1",
-                    reason="all 4,194,304 rows take minutes of oracle time on 16 host "
-                           "threads (node2vec about 11); run with FW_FULL_PARITY=1")
-@pytest.mark.parametrize("recipe", ["rmat22_n2v", "rmat22_deepwalk", "rmat22_ppr"])
-def test_rmat22_all_rows(recipe):
-    """Every row of an R-MAT-22 workload (4,194,304 queries, up to 80 hops)
-    in the bench's launch configuration against the oracle, in slices of
-    65,536 queries (progress on stdout)."""
+                    reason="all rows take minutes of oracle time on 16 host threads "
+                           "(R-MAT-22 node2vec about 11); run with FW_FULL_PARITY=1")
+@pytest.mark.parametrize("recipe", ["rmat22_n2v", "rmat22_deepwalk", "rmat22_ppr",
+                                    "chunglu24_metapath"])
+def test_all_rows(recipe):
+    """Every row of a workload (R-MAT-22: 4,194,304 queries, up to 80 hops;
+    Chung-Lu 2^24 MetaPath: 16,777,216 queries, 20 hops) in the bench's
+    launch configuration against the oracle, in slices of 65,536 queries
+    (progress on stdout)."""
     torch = torch_or_skip()
     from paper_2404_08364_amd import flowwalk as fw
     g = synth.load_recipe_graph(recipe)
